@@ -1,0 +1,218 @@
+/*
+ * ri.h - C ABI of the MI355X (gfx950) library for the per-iteration hot path of the
+ * randomised primal-dual (PD) forward-backward solver for radio-interferometric imaging
+ * of Onose, Carrillo, McEwen & Wiaux, "A randomised primal-dual algorithm for
+ * distributed radio-interferometric imaging" (2016).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Return value: RI_OK (0) or a negative RI_E* code.  ri_last_error() then returns a
+ *   message for the calling thread.  Nothing aborts and no exception crosses the ABI.
+ * Pointers: arguments documented "device" are device pointers owned by the caller; the
+ *   library never frees them and only touches them in work it enqueues on `stream`.
+ *   Arguments documented "host" are read (or written) before the call returns.
+ * Streams: every operator call only enqueues work on `stream` (a hipStream_t; NULL is
+ *   the null stream) and returns without synchronising, unless documented otherwise.
+ *   Calls on one handle that overlap on different streams race.
+ * Images: n x n row-major float32, pixel (r, c) at centred coordinates
+ *   (l_y, l_x) = (r - n/2, c - n/2).  n is a power of two, 16 <= n <= 2048.
+ * Visibilities: complex float32, interleaved (re, im), M of them, stacked by data block
+ *   as y = [y_1; ...; y_d] (Eq. 8).  Inside each block the library sorts visibilities
+ *   into its own *plan order* (by grid tile and cell); every device visibility array
+ *   passed to or returned by the library is in plan order.  ri_plan_order() returns the
+ *   map so the caller can permute its data once (see ri_plan_permute).
+ * Masks: uint8 per block, nonzero = active (the set A of Algorithm 1, step 3).  A NULL
+ *   mask means all blocks.
+ * u-v coordinates: (u, v) pairs in rad/px, u pairing with the column (x) axis; a
+ *   visibility measures sum_p x_p exp(-i (u l_x + v l_y)) (the sign of Eq. 1).
+ */
+#ifndef RI_H_
+#define RI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RI_OK = 0,
+  RI_EINVAL = -1, /* bad argument (size, range, NULL, unsupported option)      */
+  RI_ENOMEM = -2, /* a device or host allocation failed                         */
+  RI_EHIP = -3,   /* a HIP runtime call failed (message has the HIP error)      */
+  RI_ESTATE = -4  /* handle in the wrong state for the call                     */
+};
+
+typedef struct ri_plan_s* ri_plan;
+typedef struct ri_sara_s* ri_sara;
+typedef struct ri_pd_s* ri_pd;
+
+/* Message of the last failing call on this thread ("" if none).  Owned by the library. */
+const char* ri_last_error(void);
+/* Library version, major * 10000 + minor * 100 + patch. */
+int ri_version(void);
+/* HIP runtime version the library is linked against (hipRuntimeGetVersion). */
+int ri_hip_runtime_version(int* out);
+
+/* ------------------------------------------------------------------------------------
+ * Measurement operator Phi = G M F Z (Eq. 3 with the block split of Eq. 8)
+ *
+ * Z zero-pads the n x n image onto a K x K grid, K = 2n (oversampling k = 4 grid points
+ * per pixel, Sec. V) and pre-compensates the interpolation with
+ * S = 1/(phi_hat(l_y/K) phi_hat(l_x/K)); F is the unnormalised 2D DFT; G interpolates each
+ * visibility from the J x J grid cells floor(kappa) - J/2 + 1 + j, kappa = u K / (2 pi),
+ * with the Kaiser-Bessel weights phi(t) = I0(beta sqrt(1 - (2t/J)^2)) / I0(beta); M_i is
+ * the set of grid cells block i touches.
+ * ------------------------------------------------------------------------------------ */
+
+/* Tuning knobs of a plan.  Zero fields take the defaults. */
+typedef struct {
+  int tile;           /* grid tile side in cells (16, 32 or 64; default 32)            */
+  int bin;            /* max visibilities per work item (default 1024)                 */
+  int fft_panel;      /* columns per workgroup in the column FFT passes (default auto) */
+  int persistent_wgs; /* workgroups of the persistent gather/scatter kernels (auto)    */
+} ri_tuning;
+
+/*
+ * Build a plan.  uv_host: M (u, v) float32 pairs in rad/px (host, user order);
+ * block_off_host: d+1 offsets, block i = rows [block_off[i], block_off[i+1]) (host);
+ * every block must be nonempty.  J must be 8; beta <= 0 selects 2.34 J.  tune may be NULL.
+ * Allocates device memory; synchronises `stream` before returning.
+ * Errors: RI_EINVAL (n not a power of two in [16, 2048], M < 1, d < 1, empty block,
+ * offsets not increasing, non-finite u-v), RI_ENOMEM, RI_EHIP.
+ */
+int ri_plan_create(ri_plan* out, int n, int64_t M, const float* uv_host, int d,
+                   const int64_t* block_off_host, int J, double beta, const ri_tuning* tune,
+                   hipStream_t stream);
+void ri_plan_destroy(ri_plan plan);
+/* Sizes of a plan (any pointer may be NULL). */
+int ri_plan_info(ri_plan plan, int* n, int64_t* M, int* d, int* K, int* tile, int* n_items);
+/* order_host[k] = user index of the visibility at plan position k (host, M int64). */
+int ri_plan_order(ri_plan plan, int64_t* order_host);
+/* Permute complex visibilities between user and plan order on the device.
+ * to_plan != 0: dst[k] = src[order[k]]; else dst[order[k]] = src[k].  src != dst. */
+int ri_plan_permute(ri_plan plan, const float* src, float* dst, int to_plan, hipStream_t stream);
+
+/* y_i = Phi_i x for every block i with mask[i] != 0 (Algorithm 1 steps 4-5 and G_i b_i).
+ * x: device n*n float32; y: device M complex (plan order); rows of inactive blocks are
+ * left untouched.  mask: device d uint8 or NULL. */
+int ri_phi(ri_plan plan, const float* x, float* y, const uint8_t* mask, hipStream_t stream);
+
+/* x = Re sum_{i: mask[i]} Phi_i^dagger y_i = Re Z^dagger F^dagger sum_i M_i^dagger G_i^dagger y_i
+ * (the image-domain adjoint used by Algorithm 1 step 17, real part as in Eq. 12).
+ * y: device M complex (plan order); x: device n*n float32 (overwritten). */
+int ri_phi_adj(ri_plan plan, const float* y, float* x, const uint8_t* mask, hipStream_t stream);
+
+/* out[i] = ||y_i||_2^2 for every block i, accumulated in FP64 (y: device M complex, plan
+ * order; out: device d float64).  With y the data this is Eq. 13's residual at x = 0. */
+int ri_block_sumsq(ri_plan plan, const float* y, double* out, hipStream_t stream);
+
+/* ||Phi||_S on real images: power iteration on x -> Re Phi^dagger Phi x (Sec. V), with
+ * FP64 reductions.  x0: device n*n float32 start vector (caller-drawn; overwritten by the
+ * last iterate).  Stops when the eigenvalue estimate changes by <= rtol relatively or
+ * after max_it iterations.  Synchronises `stream`.  norm_host, iters_host: host outputs
+ * (iters_host may be NULL). */
+int ri_phi_norm(ri_plan plan, float* x0, int max_it, double rtol, double* norm_host,
+                int* iters_host, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * SARA sparsity dictionary Psi (Sec. III): the concatenation, without normalisation, of
+ * the Dirac basis and the Daubechies db1..db8 wavelet bases, each a `levels`-level
+ * periodic separable 2D DWT, so Psi Psi^dagger = 9 I and ||Psi||_S = 3.  Coefficients:
+ * float32 [b][n][n], basis 0 = Dirac, basis k = db_k; inside a basis the Mallat layout
+ * (per level, the m x m top-left region holds [[LL, low-y/high-x], [high-y/low-x, HH]]).
+ * Analysis of one level: a[k] = sum_j h[j] x[(2k+j) mod m], detail with
+ * g[j] = (-1)^j h[2N-1-j], the minimum-phase Daubechies lowpass h with sum h = sqrt 2.
+ * ------------------------------------------------------------------------------------ */
+
+/* bases: bit 0 = Dirac, bit k (1..8) = db_k; 0 selects all nine.  n divisible by
+ * 2^levels, 1 <= levels <= 6.  Errors: RI_EINVAL, RI_ENOMEM, RI_EHIP. */
+int ri_sara_create(ri_sara* out, int n, int levels, uint32_t bases, hipStream_t stream);
+void ri_sara_destroy(ri_sara sara);
+/* Number of bases b. */
+int ri_sara_bases(ri_sara sara, int* b);
+/* x = Psi s (s: device b*n*n float32; x: device n*n float32, overwritten). */
+int ri_psi(ri_sara sara, const float* s, float* x, hipStream_t stream);
+/* s = Psi^dagger x (x: device n*n float32; s: device b*n*n float32, overwritten). */
+int ri_psi_adj(ri_sara sara, const float* x, float* s, hipStream_t stream);
+/* ||Psi||_S by power iteration on x -> Psi Psi^dagger x; see ri_phi_norm. */
+int ri_psi_norm(ri_sara sara, float* x0, int max_it, double rtol, double* norm_host,
+                int* iters_host, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * Algorithm 1: randomised forward-backward primal-dual iterations.
+ * ------------------------------------------------------------------------------------ */
+
+typedef struct {
+  double tau;       /* primal step (Sec. V: 0.49)                                     */
+  double sigma;     /* sparsity dual step (1/||Psi||^2)                                */
+  double varsigma;  /* data dual step (1/||Phi||^2)                                    */
+  double kappa;     /* normalised soft-threshold (1e-3); threshold = kappa ||Psi||_S  */
+  double psi_norm;  /* ||Psi||_S                                                      */
+  double phi_norm;  /* ||Phi||_S, used only to check tau(sigma||Psi||^2 + varsigma||Phi||^2) < 1 */
+} ri_pd_params;
+
+/*
+ * Create a solver state.  y: device M complex (plan order), copied; eps_host: d radii
+ * eps_i of the balls B_i (host).  x, x~, s, v, v~ start at zero.  The plan and the
+ * dictionary must outlive the solver.  Errors: RI_EINVAL (sizes differ, eps_i <= 0,
+ * tau, sigma, varsigma or kappa <= 0, convergence condition >= 1), RI_ENOMEM, RI_EHIP.
+ */
+int ri_pd_create(ri_pd* out, ri_plan plan, ri_sara sara, const float* y, const double* eps_host,
+                 const ri_pd_params* params, hipStream_t stream);
+void ri_pd_destroy(ri_pd pd);
+
+/*
+ * One iteration, steps 3-18, for the active blocks mask[i] != 0 (device d uint8,
+ * NULL = all), all active blocks of uneven size in one persistent launch per operator.
+ * stats: device d x 2 float64 output; for active block i, stats[2i] = ||v_i + G_i b_i - y_i||^2
+ * (the projection's residual) and stats[2i+1] = ||G_i b_i - y_i||^2 = ||Phi_i x~ - y_i||^2
+ * (drives Eq. 13); inactive rows are set to NaN.  May be NULL.
+ * Graph capture: the call only enqueues kernels (no allocation, no host sync, no memset);
+ * the mask and stats pointers are baked into a captured graph.
+ */
+int ri_pd_step(ri_pd pd, const uint8_t* mask, double* stats, hipStream_t stream);
+
+/* The same iteration in the plain form: one launch per active block for each data-term
+ * operator, no persistent worklist.  mask_host: host d uint8 (NULL = all). */
+int ri_pd_step_plain(ri_pd pd, const uint8_t* mask_host, double* stats, hipStream_t stream);
+
+/* Rebuild sum_i M_i^dagger v~_i from the stored v (all blocks).  The batched and plain steps
+ * update that sum by differences in FP32; calling this every few tens of iterations bounds
+ * the accumulated rounding.  Enqueue-only (graph-capturable). */
+int ri_pd_refresh(ri_pd pd, hipStream_t stream);
+
+/* State access for checkpoint / resume and inspection.  which: */
+enum {
+  RI_PD_X = 0,     /* n*n float32                                   */
+  RI_PD_XTILDE = 1,/* n*n float32                                   */
+  RI_PD_S = 2,     /* b*n*n float32                                 */
+  RI_PD_V = 3,     /* M complex float32, plan order                 */
+  RI_PD_ITER = 4   /* int64 iteration counter (host buffer)         */
+};
+/* Copy state `which` to/from buf (device, or host for RI_PD_ITER), `bytes` long.
+ * ri_pd_set recomputes sum_i M_i^dagger v~_i from the stored v when V is set. */
+int ri_pd_get(ri_pd pd, int which, void* buf, size_t bytes, hipStream_t stream);
+int ri_pd_set(ri_pd pd, int which, const void* buf, size_t bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * Adaptive probabilities (Sec. IV)
+ * ------------------------------------------------------------------------------------ */
+
+/* Eq. 13 on the host: c[i] = max(resid_norm[i] - eps[i], 0)^2 / eps[i]^2. */
+int ri_residual_energy(const double* resid_norm, const double* eps, int d, double* c_out);
+
+/* Eq. 14 on the host: p_i = p_min + min((n - d p_min) c_i / sum c + a, p_max - p_min), with
+ * a >= 0 the smallest value giving sum p = n; p_i = n/d when sum c = 0.
+ * Needs 0 < p_min <= n/d <= p_max <= 1 and c_i >= 0 (RI_EINVAL otherwise).  a_out may be NULL. */
+int ri_probs(const double* c, int d, double n_nodes, double p_min, double p_max, double* p_out,
+             double* a_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RI_H_ */

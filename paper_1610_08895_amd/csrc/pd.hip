@@ -1,0 +1,274 @@
+// Algorithm 1, randomised forward-backward primal-dual, one iteration per call.
+//
+// Data-fidelity branch (steps 4-11): b~ = F Z x~; for active blocks e = G_i b_i - y_i with
+// FP64 block norms; v_i <- (v_i + e) max(0, 1 - eps_i / ||v_i + e||); the change of
+// G_i^dagger v_i is added to the running sum sum_i M_i^dagger v~_i, which therefore holds
+// the latest v~_i of active blocks and the kept v~_i of inactive ones (step 11); then
+// g = Re Z^dagger F^dagger (that sum).
+// Sparsity branch (steps 13-14): s <- clip(s + Psi^dagger x~, -alpha, alpha), then the
+// synthesis levels of Psi s below the finest.
+// The two branches depend only on x~ of the previous iteration (the paper runs them
+// concurrently); the batched step forks the sparsity branch onto a side stream and joins
+// before the last kernel, which finishes Psi s and applies steps 17-18.
+//
+// The running sum is kept in FP32 and updated by differences; ri_pd_refresh (and setting
+// V) rebuilds it from the stored v, bounding accumulated rounding.
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "handles.hpp"
+#include "sara.hpp"
+
+struct ri_pd_s {
+  ri::Plan* plan = nullptr;
+  ri::Sara* sara = nullptr;
+  ri_pd_params prm{};
+  float alpha = 0.f;
+  float2* y = nullptr;
+  float2* v = nullptr;
+  float2* e = nullptr;
+  float* x = nullptr;
+  float* xt = nullptr;
+  float* s = nullptr;
+  float* g = nullptr;
+  float2* sum = nullptr;   // sum_i M_i^dagger v~_i on the K x K grid
+  double* eps = nullptr;   // d
+  double* stats = nullptr; // d x 2
+  uint8_t* mask_dev = nullptr;
+  int64_t iter = 0;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+};
+
+namespace ri {
+namespace {
+
+__global__ void k_export_stats(const uint8_t* __restrict__ mask, const double* __restrict__ in,
+                               double* __restrict__ out, int d) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d; i += gridDim.x * blockDim.x) {
+    const bool act = mask == nullptr || mask[i] != 0;
+    out[2 * i] = act ? in[2 * i] : __builtin_nan("");
+    out[2 * i + 1] = act ? in[2 * i + 1] : __builtin_nan("");
+  }
+}
+
+void destroy_pd(ri_pd_s* P) {
+  dev_free(P->y);
+  dev_free(P->v);
+  dev_free(P->e);
+  dev_free(P->x);
+  dev_free(P->xt);
+  dev_free(P->s);
+  dev_free(P->g);
+  dev_free(P->sum);
+  dev_free(P->eps);
+  dev_free(P->stats);
+  dev_free(P->mask_dev);
+  if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
+  if (P->ev_join) (void)hipEventDestroy(P->ev_join);
+  if (P->side) (void)hipStreamDestroy(P->side);
+}
+
+int refresh_sum(ri_pd_s* P, hipStream_t s) {
+  const Plan& p = *P->plan;
+  RI_TRY(zero_c64(P->sum, size_t(p.K) * p.K, s));
+  return grid_all(p, P->v, P->sum, s);
+}
+
+int export_stats(ri_pd_s* P, const uint8_t* mask, double* stats, hipStream_t s) {
+  if (!stats) return RI_OK;
+  hipLaunchKernelGGL(k_export_stats, dim3((P->plan->d + 255) / 256), dim3(256), 0, s, mask, P->stats, stats,
+                     P->plan->d);
+  RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+int sparsity_branch(ri_pd_s* P, hipStream_t s) {
+  // step 13 (Moreau form of the soft-threshold), then Psi s below the finest level
+  RI_TRY(psi_adj_apply(*P->sara, P->xt, P->s, true, P->alpha, s));
+  return psi_synth_lower(*P->sara, P->s, s);
+}
+
+int primal_update(ri_pd_s* P, hipStream_t s) {
+  PrimalUpdate u{P->g, P->x, P->xt, float(P->prm.tau), float(P->prm.sigma), float(P->prm.varsigma)};
+  return psi_top_update(*P->sara, P->s, u, s);
+}
+
+}  // namespace
+}  // namespace ri
+
+using ri::fail;
+
+extern "C" {
+
+int ri_pd_create(ri_pd* out, ri_plan plan, ri_sara sara, const float* y, const double* eps_host,
+                 const ri_pd_params* params, hipStream_t stream) {
+  if (!out || !plan || !sara || !y || !eps_host || !params) return fail(RI_EINVAL, "NULL argument");
+  *out = nullptr;
+  ri::Plan& p = plan->p;
+  ri::Sara& S = sara->s;
+  if (S.n != p.n) return fail(RI_EINVAL, "image sizes differ (plan %d, dictionary %d)", p.n, S.n);
+  const ri_pd_params& q = *params;
+  if (!(q.tau > 0 && q.sigma > 0 && q.varsigma > 0 && q.kappa > 0 && q.psi_norm > 0 && q.phi_norm > 0))
+    return fail(RI_EINVAL, "tau, sigma, varsigma, kappa and the norms must be positive");
+  const double cond = q.tau * (q.sigma * q.psi_norm * q.psi_norm + q.varsigma * q.phi_norm * q.phi_norm);
+  if (!(cond < 1.0)) return fail(RI_EINVAL, "tau (sigma ||Psi||^2 + varsigma ||Phi||^2) = %.6g must be < 1", cond);
+  for (int i = 0; i < p.d; ++i)
+    if (!(eps_host[i] > 0)) return fail(RI_EINVAL, "eps[%d] must be positive", i);
+
+  ri_pd_s* P = new (std::nothrow) ri_pd_s;
+  if (!P) return fail(RI_ENOMEM, "host allocation failed");
+  P->plan = &p;
+  P->sara = &S;
+  P->prm = q;
+  P->alpha = float(q.kappa * q.psi_norm);
+  const size_t N = size_t(p.n) * p.n, M = size_t(p.M), KK = size_t(p.K) * p.K;
+  int rc = RI_OK;
+  auto step = [&](int r) {
+    if (rc == RI_OK) rc = r;
+  };
+  step(ri::dev_alloc(&P->y, M));
+  step(ri::dev_alloc(&P->v, M));
+  step(ri::dev_alloc(&P->e, M));
+  step(ri::dev_alloc(&P->x, N));
+  step(ri::dev_alloc(&P->xt, N));
+  step(ri::dev_alloc(&P->s, size_t(S.b) * N));
+  step(ri::dev_alloc(&P->g, N));
+  step(ri::dev_alloc(&P->sum, KK));
+  step(ri::dev_alloc(&P->eps, size_t(p.d)));
+  step(ri::dev_alloc(&P->stats, 2 * size_t(p.d)));
+  step(ri::dev_alloc(&P->mask_dev, size_t(p.d)));
+  if (rc == RI_OK && hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess)
+    rc = fail(RI_EHIP, "side stream creation failed");
+  if (rc == RI_OK && (hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming) != hipSuccess ||
+                      hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming) != hipSuccess))
+    rc = fail(RI_EHIP, "event creation failed");
+  if (rc == RI_OK && hipMemcpyAsync(P->y, y, M * sizeof(float2), hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    rc = fail(RI_EHIP, "copy of y failed");
+  if (rc == RI_OK &&
+      hipMemcpyAsync(P->eps, eps_host, p.d * sizeof(double), hipMemcpyHostToDevice, stream) != hipSuccess)
+    rc = fail(RI_EHIP, "copy of eps failed");
+  step(rc == RI_OK ? ri::zero_c64(P->v, M, stream) : rc);
+  step(rc == RI_OK ? ri::zero_c64(P->e, M, stream) : rc);
+  step(rc == RI_OK ? ri::zero_f32(P->x, N, stream) : rc);
+  step(rc == RI_OK ? ri::zero_f32(P->xt, N, stream) : rc);
+  step(rc == RI_OK ? ri::zero_f32(P->s, size_t(S.b) * N, stream) : rc);
+  step(rc == RI_OK ? ri::zero_f32(P->g, N, stream) : rc);
+  step(rc == RI_OK ? ri::zero_c64(P->sum, KK, stream) : rc);
+  if (rc == RI_OK && hipStreamSynchronize(stream) != hipSuccess) rc = fail(RI_EHIP, "stream sync failed");
+  if (rc != RI_OK) {
+    ri::destroy_pd(P);
+    delete P;
+    return rc;
+  }
+  *out = P;
+  return RI_OK;
+}
+
+void ri_pd_destroy(ri_pd pd) {
+  if (!pd) return;
+  ri::destroy_pd(pd);
+  delete pd;
+}
+
+int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) {
+  if (!P) return fail(RI_EINVAL, "pd is NULL");
+  const ri::Plan& p = *P->plan;
+  // fork: the sparsity branch needs only x~ of the previous iteration
+  RI_HIP(hipEventRecord(P->ev_fork, stream));
+  RI_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+  RI_TRY(ri::sparsity_branch(P, P->side));
+  RI_HIP(hipEventRecord(P->ev_join, P->side));
+  // data-fidelity branch
+  RI_TRY(ri::build_active(p, mask, P->stats, stream));
+  RI_TRY(ri::fft_forward(p, P->xt, p.grid, stream));
+  RI_TRY(ri::degrid_residual(p, p.grid, P->y, P->v, P->e, P->stats, p.active_list, p.active_count, 0, 0, stream));
+  RI_TRY(ri::grid_project(p, P->e, P->v, P->stats, P->eps, P->sum, p.active_list, p.active_count, 0, 0, stream));
+  RI_TRY(ri::fft_adjoint(p, P->sum, P->g, stream));
+  RI_TRY(ri::export_stats(P, mask, stats, stream));
+  // join, then Psi s and the primal update
+  RI_HIP(hipStreamWaitEvent(stream, P->ev_join, 0));
+  RI_TRY(ri::primal_update(P, stream));
+  P->iter += 1;
+  return RI_OK;
+}
+
+int ri_pd_step_plain(ri_pd P, const uint8_t* mask_host, double* stats, hipStream_t stream) {
+  if (!P) return fail(RI_EINVAL, "pd is NULL");
+  const ri::Plan& p = *P->plan;
+  std::vector<uint8_t> ones;
+  if (!mask_host) {
+    ones.assign(p.d, 1);
+    mask_host = ones.data();
+  }
+  RI_HIP(hipMemcpyAsync(P->mask_dev, mask_host, p.d, hipMemcpyHostToDevice, stream));
+  RI_TRY(ri::build_active(p, P->mask_dev, P->stats, stream));  // zeroes the active blocks' sums
+  RI_TRY(ri::fft_forward(p, P->xt, p.grid, stream));
+  for (int i = 0; i < p.d; ++i) {
+    if (!mask_host[i]) continue;
+    const int a = p.item_off_host[i], b = p.item_off_host[i + 1];
+    RI_TRY(ri::degrid_residual(p, p.grid, P->y, P->v, P->e, P->stats, nullptr, nullptr, a, b - a, stream));
+  }
+  for (int i = 0; i < p.d; ++i) {
+    if (!mask_host[i]) continue;
+    const int a = p.item_off_host[i], b = p.item_off_host[i + 1];
+    RI_TRY(ri::grid_project(p, P->e, P->v, P->stats, P->eps, P->sum, nullptr, nullptr, a, b - a, stream));
+  }
+  RI_TRY(ri::fft_adjoint(p, P->sum, P->g, stream));
+  RI_TRY(ri::export_stats(P, P->mask_dev, stats, stream));
+  RI_TRY(ri::sparsity_branch(P, stream));
+  RI_TRY(ri::primal_update(P, stream));
+  P->iter += 1;
+  return RI_OK;
+}
+
+int ri_pd_refresh(ri_pd P, hipStream_t stream) {
+  if (!P) return fail(RI_EINVAL, "pd is NULL");
+  return ri::refresh_sum(P, stream);
+}
+
+int ri_pd_get(ri_pd P, int which, void* buf, size_t bytes, hipStream_t stream) {
+  if (!P || !buf) return fail(RI_EINVAL, "NULL argument");
+  const size_t N = size_t(P->plan->n) * P->plan->n;
+  const void* src = nullptr;
+  size_t need = 0;
+  switch (which) {
+    case RI_PD_X: src = P->x; need = N * 4; break;
+    case RI_PD_XTILDE: src = P->xt; need = N * 4; break;
+    case RI_PD_S: src = P->s; need = size_t(P->sara->b) * N * 4; break;
+    case RI_PD_V: src = P->v; need = size_t(P->plan->M) * 8; break;
+    case RI_PD_ITER:
+      if (bytes != sizeof(int64_t)) return fail(RI_EINVAL, "ITER needs %zu bytes", sizeof(int64_t));
+      *static_cast<int64_t*>(buf) = P->iter;
+      return RI_OK;
+    default: return fail(RI_EINVAL, "unknown state %d", which);
+  }
+  if (bytes != need) return fail(RI_EINVAL, "state %d needs %zu bytes, got %zu", which, need, bytes);
+  RI_HIP(hipMemcpyAsync(buf, src, bytes, hipMemcpyDeviceToDevice, stream));
+  return RI_OK;
+}
+
+int ri_pd_set(ri_pd P, int which, const void* buf, size_t bytes, hipStream_t stream) {
+  if (!P || !buf) return fail(RI_EINVAL, "NULL argument");
+  const size_t N = size_t(P->plan->n) * P->plan->n;
+  void* dst = nullptr;
+  size_t need = 0;
+  switch (which) {
+    case RI_PD_X: dst = P->x; need = N * 4; break;
+    case RI_PD_XTILDE: dst = P->xt; need = N * 4; break;
+    case RI_PD_S: dst = P->s; need = size_t(P->sara->b) * N * 4; break;
+    case RI_PD_V: dst = P->v; need = size_t(P->plan->M) * 8; break;
+    case RI_PD_ITER:
+      if (bytes != sizeof(int64_t)) return fail(RI_EINVAL, "ITER needs %zu bytes", sizeof(int64_t));
+      P->iter = *static_cast<const int64_t*>(buf);
+      return RI_OK;
+    default: return fail(RI_EINVAL, "unknown state %d", which);
+  }
+  if (bytes != need) return fail(RI_EINVAL, "state %d needs %zu bytes, got %zu", which, need, bytes);
+  RI_HIP(hipMemcpyAsync(dst, buf, bytes, hipMemcpyDeviceToDevice, stream));
+  if (which == RI_PD_V) return ri::refresh_sum(P, stream);
+  return RI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,317 @@
+// Measurement-operator plan and the Phi / Phi^dagger entry points (Eq. 3, Eq. 8).
+//
+// Plan creation, on the host in FP64:
+//   * each u-v coordinate becomes kappa = u K / (2 pi) wrapped to [0, K), stored as a
+//     12-bit cell plus a 20-bit fraction (position error <= 2^-21 cell, i.e. < 1e-6 rad of
+//     phase at the image edge);
+//   * inside each block, visibilities are sorted by (grid tile, cell) and cut into work
+//     items of at most `bin` visibilities of one tile;
+//   * Kaiser-Bessel weights are fitted per tap by degree-9 polynomials (Chebyshev
+//     interpolation of the kernel evaluated with an I0 power series);
+//   * twiddles exp(-2 pi i k / K) and the pre-compensation S = 1/phi_hat(l/K) are
+//     evaluated in FP64 and rounded to FP32.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "host_math.hpp"
+#include "handles.hpp"
+
+namespace ri {
+namespace {
+
+__global__ void k_permute(const float2* __restrict__ src, float2* __restrict__ dst,
+                          const int64_t* __restrict__ order, int64_t M, int to_plan) {
+  for (int64_t k = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; k < M; k += int64_t(gridDim.x) * blockDim.x) {
+    if (to_plan) dst[k] = src[order[k]];
+    else dst[order[k]] = src[k];
+  }
+}
+
+__global__ void k_copy_f32(const float* __restrict__ a, float* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    b[i] = a[i];
+}
+
+uint32_t pack_coord(double kappa, int K) {
+  double w = kappa - K * std::floor(kappa / K);  // [0, K]
+  long long cell = (long long)std::floor(w);
+  long long f = std::llround((w - double(cell)) * double(1u << FRAC_BITS));
+  if (f >= (1LL << FRAC_BITS)) {
+    f = 0;
+    cell += 1;
+  }
+  cell %= K;
+  if (cell < 0) cell += K;
+  return (uint32_t(cell) << FRAC_BITS) | uint32_t(f);
+}
+
+void destroy_plan(Plan& p) {
+  dev_free(p.coord);
+  dev_free(p.order);
+  dev_free(p.items);
+  dev_free(p.item_off);
+  dev_free(p.twiddle);
+  dev_free(p.scale);
+  dev_free(p.grid);
+  dev_free(p.rowbuf);
+  dev_free(p.active_list);
+  dev_free(p.active_count);
+  dev_free(p.norm_tmp);
+  dev_free(p.dsum);
+}
+
+int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t* off, int J, double beta,
+                const ri_tuning* tune, hipStream_t s) {
+  if (!is_pow2(n) || n < 16 || n > 2048) return fail(RI_EINVAL, "n=%d must be a power of two in [16, 2048]", n);
+  if (M < 1 || M > (int64_t(1) << 31) - 1) return fail(RI_EINVAL, "M=%lld out of range", (long long)M);
+  if (d < 1) return fail(RI_EINVAL, "d=%d must be >= 1", d);
+  if (!uv || !off) return fail(RI_EINVAL, "uv and block_off must not be NULL");
+  if (J != KB_J) return fail(RI_EINVAL, "only J=%d is supported (got %d)", KB_J, J);
+  if (off[0] != 0 || off[d] != M) return fail(RI_EINVAL, "block_off must start at 0 and end at M");
+  for (int i = 0; i < d; ++i)
+    if (off[i + 1] <= off[i]) return fail(RI_EINVAL, "block %d is empty or offsets decrease", i);
+  for (int64_t m = 0; m < 2 * M; ++m)
+    if (!std::isfinite(uv[m])) return fail(RI_EINVAL, "non-finite u-v coordinate at %lld", (long long)(m / 2));
+
+  p.n = n;
+  p.K = 2 * n;
+  p.M = M;
+  p.d = d;
+  p.J = J;
+  p.beta = beta > 0 ? beta : 2.34 * J;
+  p.tile = tune && tune->tile ? tune->tile : 32;
+  if (p.tile != 16 && p.tile != 32 && p.tile != 64) return fail(RI_EINVAL, "tile must be 16, 32 or 64");
+  if (p.tile > p.K) p.tile = 16;
+  p.bin = tune && tune->bin > 0 ? tune->bin : 1024;
+  p.fft_panel = tune ? tune->fft_panel : 0;
+  p.persistent_wgs = tune ? tune->persistent_wgs : 0;
+  p.tpa = p.K / p.tile;
+  p.block_off_host.assign(off, off + d + 1);
+
+  // Kaiser-Bessel polynomials
+  std::vector<double> mono;
+  kb_fit_taps(J, p.beta, 2 * KB_HALF_DEG + 1, mono, &p.poly_err);
+  if (!(p.poly_err < 1e-8)) return fail(RI_EINVAL, "kernel polynomial fit error %.3g too large (beta %.3f)", p.poly_err, p.beta);
+  for (int j = 0; j < KB_J / 2; ++j)
+    for (int k = 0; k <= KB_HALF_DEG; ++k) {
+      p.poly.e[j][k] = float(mono[size_t(j) * (2 * KB_HALF_DEG + 2) + 2 * k]);
+      p.poly.o[j][k] = float(mono[size_t(j) * (2 * KB_HALF_DEG + 2) + 2 * k + 1]);
+    }
+
+  // coordinates, sort and work items (blocks are independent: one host thread each)
+  const int K = p.K, T = p.tile, tpa = p.tpa;
+  std::vector<uint2> packed(M);
+  std::vector<uint64_t> keys(M);
+  const double to_cells = double(K) / (2.0 * M_PI);
+  p.order_host.resize(M);
+  std::vector<std::vector<Item>> block_items(d);
+  const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto work = [&](int i) {
+    const int64_t lo = off[i], hi = off[i + 1];
+    std::vector<std::pair<uint64_t, int64_t>> kv(hi - lo);
+    for (int64_t m = lo; m < hi; ++m) {
+      const uint32_t cx = pack_coord(double(uv[2 * m]) * to_cells, K);
+      const uint32_t cy = pack_coord(double(uv[2 * m + 1]) * to_cells, K);
+      packed[m] = make_uint2(cx, cy);
+      const uint32_t gx = cx >> FRAC_BITS, gy = cy >> FRAC_BITS;
+      const uint64_t tile = uint64_t(gy / T) * tpa + gx / T;
+      const uint64_t local = uint64_t(gy % T) * T + gx % T;
+      kv[m - lo] = {(tile << 32) | local, m};
+    }
+    std::sort(kv.begin(), kv.end());
+    for (int64_t k = 0; k < hi - lo; ++k) p.order_host[lo + k] = kv[k].second;
+    auto& its = block_items[i];
+    int64_t k = 0;
+    while (k < hi - lo) {
+      const uint64_t tile = kv[k].first >> 32;
+      int64_t e = k;
+      while (e < hi - lo && (kv[e].first >> 32) == tile) ++e;
+      for (int64_t a = k; a < e; a += p.bin)
+        its.push_back(make_int4(i, int(tile), int(lo + a), int(std::min<int64_t>(p.bin, e - a))));
+      k = e;
+    }
+  };
+  {
+    std::vector<std::thread> th;
+    std::atomic<int> next{0};
+    for (unsigned t = 0; t < nthreads; ++t)
+      th.emplace_back([&] {
+        for (int i = next++; i < d; i = next++) work(i);
+      });
+    for (auto& t : th) t.join();
+  }
+  std::vector<uint2> coord_sorted(M);
+  for (int64_t k = 0; k < M; ++k) coord_sorted[k] = packed[p.order_host[k]];
+  std::vector<Item> items;
+  p.item_off_host.assign(d + 1, 0);
+  for (int i = 0; i < d; ++i) {
+    p.item_off_host[i] = int(items.size());
+    items.insert(items.end(), block_items[i].begin(), block_items[i].end());
+  }
+  p.item_off_host[d] = int(items.size());
+  p.n_items = int(items.size());
+
+  std::vector<float2> tw(K);
+  for (int k = 0; k < K; ++k) {
+    const double a = -2.0 * M_PI * k / K;
+    tw[k] = make_float2(float(std::cos(a)), float(std::sin(a)));
+  }
+  std::vector<float> sc(n);
+  for (int r = 0; r < n; ++r) sc[r] = float(1.0 / kb_hat(double(r - n / 2) / K, J, p.beta));
+
+  RI_TRY(dev_alloc(&p.coord, M));
+  RI_TRY(dev_alloc(&p.order, M));
+  RI_TRY(dev_alloc(&p.items, items.size()));
+  RI_TRY(dev_alloc(&p.item_off, d + 1));
+  RI_TRY(dev_alloc(&p.twiddle, K));
+  RI_TRY(dev_alloc(&p.scale, n));
+  RI_TRY(dev_alloc(&p.grid, size_t(K) * K));
+  RI_TRY(dev_alloc(&p.rowbuf, size_t(n) * K));
+  RI_TRY(dev_alloc(&p.active_list, items.size()));
+  RI_TRY(dev_alloc(&p.active_count, 1));
+  RI_TRY(dev_alloc(&p.norm_tmp, size_t(n) * n));
+  RI_TRY(dev_alloc(&p.dsum, SUMSQ_SCRATCH));
+  RI_HIP(hipMemcpyAsync(p.coord, coord_sorted.data(), M * sizeof(uint2), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.order, p.order_host.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.item_off, p.item_off_host.data(), (d + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.twiddle, tw.data(), K * sizeof(float2), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.scale, sc.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
+  RI_HIP(hipStreamSynchronize(s));
+  return RI_OK;
+}
+
+}  // namespace
+
+int phi_apply(const Plan& p, const float* x, float* y, const uint8_t* mask, hipStream_t s) {
+  RI_TRY(build_active(p, mask, nullptr, s));
+  RI_TRY(fft_forward(p, x, p.grid, s));
+  return degrid_apply(p, p.grid, reinterpret_cast<float2*>(y), s);
+}
+
+int phi_adj_apply(const Plan& p, const float* y, float* x, const uint8_t* mask, hipStream_t s) {
+  RI_TRY(build_active(p, mask, nullptr, s));
+  RI_TRY(zero_c64(p.grid, size_t(p.K) * p.K, s));
+  RI_TRY(grid_apply(p, reinterpret_cast<const float2*>(y), p.grid, s));
+  return fft_adjoint(p, p.grid, x, s);
+}
+
+}  // namespace ri
+
+using ri::fail;
+
+extern "C" {
+
+int ri_plan_create(ri_plan* out, int n, int64_t M, const float* uv_host, int d, const int64_t* block_off_host,
+                   int J, double beta, const ri_tuning* tune, hipStream_t stream) {
+  if (!out) return fail(RI_EINVAL, "out is NULL");
+  *out = nullptr;
+  ri_plan h = new (std::nothrow) ri_plan_s;
+  if (!h) return fail(RI_ENOMEM, "host allocation failed");
+  int rc;
+  try {
+    rc = ri::create_plan(h->p, n, M, uv_host, d, block_off_host, J, beta, tune, stream);
+  } catch (const std::bad_alloc&) {
+    rc = fail(RI_ENOMEM, "host allocation failed during plan creation");
+  }
+  if (rc != RI_OK) {
+    ri::destroy_plan(h->p);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return RI_OK;
+}
+
+void ri_plan_destroy(ri_plan plan) {
+  if (!plan) return;
+  ri::destroy_plan(plan->p);
+  delete plan;
+}
+
+int ri_plan_info(ri_plan plan, int* n, int64_t* M, int* d, int* K, int* tile, int* n_items) {
+  if (!plan) return fail(RI_EINVAL, "plan is NULL");
+  if (n) *n = plan->p.n;
+  if (M) *M = plan->p.M;
+  if (d) *d = plan->p.d;
+  if (K) *K = plan->p.K;
+  if (tile) *tile = plan->p.tile;
+  if (n_items) *n_items = plan->p.n_items;
+  return RI_OK;
+}
+
+int ri_plan_order(ri_plan plan, int64_t* order_host) {
+  if (!plan || !order_host) return fail(RI_EINVAL, "NULL argument");
+  std::memcpy(order_host, plan->p.order_host.data(), plan->p.M * sizeof(int64_t));
+  return RI_OK;
+}
+
+int ri_plan_permute(ri_plan plan, const float* src, float* dst, int to_plan, hipStream_t stream) {
+  if (!plan || !src || !dst) return fail(RI_EINVAL, "NULL argument");
+  if (src == dst) return fail(RI_EINVAL, "src and dst must differ");
+  hipLaunchKernelGGL(ri::k_permute, dim3(2048), dim3(256), 0, stream, reinterpret_cast<const float2*>(src),
+                     reinterpret_cast<float2*>(dst), plan->p.order, plan->p.M, to_plan);
+  RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+int ri_phi(ri_plan plan, const float* x, float* y, const uint8_t* mask, hipStream_t stream) {
+  if (!plan || !x || !y) return fail(RI_EINVAL, "NULL argument");
+  return ri::phi_apply(plan->p, x, y, mask, stream);
+}
+
+int ri_phi_adj(ri_plan plan, const float* y, float* x, const uint8_t* mask, hipStream_t stream) {
+  if (!plan || !x || !y) return fail(RI_EINVAL, "NULL argument");
+  return ri::phi_adj_apply(plan->p, y, x, mask, stream);
+}
+
+int ri_block_sumsq(ri_plan plan, const float* y, double* out, hipStream_t stream) {
+  if (!plan || !y || !out) return fail(RI_EINVAL, "NULL argument");
+  return ri::block_sumsq(plan->p, reinterpret_cast<const float2*>(y), out, stream);
+}
+
+int ri_phi_norm(ri_plan plan, float* x0, int max_it, double rtol, double* norm_host, int* iters_host,
+                hipStream_t stream) {
+  if (!plan || !x0 || !norm_host || max_it < 1) return fail(RI_EINVAL, "bad argument");
+  ri::Plan& p = plan->p;
+  const size_t N = size_t(p.n) * p.n;
+  float* y = nullptr;
+  RI_TRY(ri::dev_alloc(&y, 2 * size_t(p.M)));
+  float* cur = x0;
+  float* nxt = p.norm_tmp;
+  double lam = 0.0, lam_prev = 0.0, sq = 0.0;
+  int it = 0, rc = RI_OK;
+  rc = ri::sumsq_f32(cur, N, p.dsum, stream);
+  if (rc == RI_OK) rc = ri::scale_by_rsqrt(cur, N, p.dsum, stream);
+  for (it = 1; rc == RI_OK && it <= max_it; ++it) {
+    rc = ri::phi_apply(p, cur, y, nullptr, stream);
+    if (rc == RI_OK) rc = ri::phi_adj_apply(p, y, nxt, nullptr, stream);
+    if (rc == RI_OK) rc = ri::sumsq_f32(nxt, N, p.dsum, stream);
+    if (rc == RI_OK && hipMemcpyAsync(&sq, p.dsum, sizeof(double), hipMemcpyDeviceToHost, stream) != hipSuccess)
+      rc = fail(RI_EHIP, "copy of the norm failed");
+    if (rc == RI_OK && hipStreamSynchronize(stream) != hipSuccess) rc = fail(RI_EHIP, "stream sync failed");
+    if (rc != RI_OK) break;
+    lam = std::sqrt(sq);
+    rc = ri::scale_by_rsqrt(nxt, N, p.dsum, stream);
+    std::swap(cur, nxt);
+    if (lam == 0.0 || std::fabs(lam - lam_prev) <= rtol * lam) break;
+    lam_prev = lam;
+  }
+  if (rc == RI_OK && cur != x0) {
+    hipLaunchKernelGGL(ri::k_copy_f32, dim3(1024), dim3(256), 0, stream, cur, x0, N);
+    if (hipGetLastError() != hipSuccess) rc = fail(RI_EHIP, "copy launch failed");
+  }
+  if (rc == RI_OK && hipStreamSynchronize(stream) != hipSuccess) rc = fail(RI_EHIP, "stream sync failed");
+  ri::dev_free(y);
+  if (rc != RI_OK) return rc;
+  *norm_host = std::sqrt(lam);
+  if (iters_host) *iters_host = std::min(it, max_it);
+  return RI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal state of a measurement-operator plan (Phi = G M F Z, Eq. 3 / Eq. 8).
+#pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
+namespace ri {
+
+// Kaiser-Bessel weights of the J = 8 taps as polynomials in x = 2 f - 1 (f the fractional
+// grid coordinate): w_j = E_j(x^2) + x O_j(x^2) and w_{7-j} = E_j(x^2) - x O_j(x^2), j < 4.
+constexpr int KB_J = 8;
+constexpr int KB_HALF_DEG = 4;  // E_j, O_j of degree 4 in x^2 (total degree 9)
+struct KBPoly {
+  float e[KB_J / 2][KB_HALF_DEG + 1];
+  float o[KB_J / 2][KB_HALF_DEG + 1];
+};
+
+// Fixed-point grid coordinate: cell index in the high 12 bits, fraction in the low 20.
+constexpr int FRAC_BITS = 20;
+constexpr unsigned FRAC_MASK = (1u << FRAC_BITS) - 1u;
+
+// A work item: up to `bin` visibilities of one block that fall in one grid tile.
+// x = block, y = tile (ty * tiles_per_axis + tx), z = first plan position, w = count.
+using Item = int4;
+
+struct Plan {
+  int n = 0, K = 0, J = KB_J, d = 0;
+  int64_t M = 0;
+  double beta = 0.0;
+  int tile = 32, bin = 1024, tpa = 0;  // tiles per axis
+  int n_items = 0;
+  int fft_panel = 0;
+  int persistent_wgs = 0;
+  KBPoly poly{};
+  double poly_err = 0.0;
+
+  std::vector<int> item_off_host;  // d + 1
+  std::vector<int64_t> order_host;  // plan position -> user index
+  std::vector<int64_t> block_off_host;
+
+  // device
+  uint2* coord = nullptr;     // M packed (x, y) coordinates, plan order
+  int64_t* order = nullptr;   // M, plan position -> user index
+  Item* items = nullptr;      // n_items
+  int* item_off = nullptr;    // d + 1
+  float2* twiddle = nullptr;  // K forward twiddles exp(-2 pi i k / K)
+  float* scale = nullptr;     // n: S along one axis, 1 / phi_hat(l / K)
+  float2* grid = nullptr;     // K * K work grid
+  float2* rowbuf = nullptr;   // n * K half-transformed rows
+  int* active_list = nullptr; // n_items
+  int* active_count = nullptr;
+  float* norm_tmp = nullptr;  // n * n scratch for power iterations
+  double* dsum = nullptr;     // FP64 reduction scratch
+};
+
+// ---- launchers implemented in fft.hip ----
+// grid = F Z S x (x: n*n real).
+int fft_forward(const Plan& p, const float* x, float2* grid, hipStream_t s);
+// x = Re S Z^dagger F^dagger grid (x: n*n real).
+int fft_adjoint(const Plan& p, const float2* grid, float* x, hipStream_t s);
+
+// ---- launchers implemented in gridding.hip ----
+// Active work list of the blocks selected by mask (NULL = all) into p.active_list.
+int build_active(const Plan& p, const uint8_t* mask, double* stats_zero, hipStream_t s);
+// out[i] = ||y_i||^2 (FP64) for every block.
+int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s);
+// y = G b for the active items (operator form).
+int degrid_apply(const Plan& p, const float2* grid, float2* y, hipStream_t s);
+// grid += G^dagger y for the active items (operator form; grid zeroed by the caller).
+int grid_apply(const Plan& p, const float2* y, float2* grid, hipStream_t s);
+// PD residual pass: e = G b - y, r = v + e; stats[2i] += ||r||^2, stats[2i+1] += ||e||^2.
+int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
+                    double* stats, const int* list, const int* count, int base, int count_host,
+                    hipStream_t s);
+// PD projection pass: v_new = (v + e) max(0, 1 - eps/||r||); grid += G^dagger (v_new - v); v = v_new.
+int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
+                 float2* grid, const int* list, const int* count, int base, int count_host,
+                 hipStream_t s);
+// grid += G^dagger v over all items (used to rebuild the running sum from scratch).
+int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s);
+
+// ---- reductions (reduce.hip) ----
+int zero_f32(float* p, size_t n, hipStream_t s);
+int zero_c64(float2* p, size_t n, hipStream_t s);
+// out[0] = sum x^2 (FP64); out holds SUMSQ_SCRATCH doubles.
+constexpr int SUMSQ_SCRATCH = 1025;
+int sumsq_f32(const float* x, size_t n, double* out, hipStream_t s);
+// x *= 1 / sqrt(*sq) (device scalar, FP64)
+int scale_by_rsqrt(float* x, size_t n, const double* sq, hipStream_t s);
+
+}  // namespace ri

@@ -1,0 +1,403 @@
+// SARA dictionary: Psi^dagger (analysis, Algorithm 1 step 13) and Psi (synthesis,
+// step 14) for the Dirac basis plus Daubechies wavelets, as periodic separable 2D filter
+// banks.  One analysis level of an m x m input, per axis:
+//   a[k] = sum_j h[j] x[(2k + j) mod m],   d[k] = sum_j g[j] x[(2k + j) mod m],
+// x (columns) first, then y (rows), written in Mallat layout; synthesis is the transpose.
+//
+// Each workgroup owns an output tile and stages the input it needs in LDS together with
+// its periodic halo (filter length - 2 samples), then runs the row and the column filters
+// from LDS.  Analysis of level 1 reads x~ once per wavelet from L2; the dual update of step
+// 13, s = clip(s + Psi^dagger x~, -alpha, alpha), is applied as each coefficient is
+// produced.  The last synthesis level sums all bases in registers and applies steps 17-18
+// (primal update and extrapolation) in the same kernel.
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "host_math.hpp"
+#include "handles.hpp"
+#include "sara.hpp"
+
+namespace ri {
+namespace {
+
+constexpr int ST = 256;  // threads per workgroup
+constexpr int TO = 16;   // analysis: outputs per subband per axis per workgroup
+constexpr int TS = 32;   // synthesis: outputs per axis per workgroup
+
+__device__ __forceinline__ int pmod(int a, int m) {
+  const int r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+__device__ __forceinline__ float clampf(float v, float a) { return fminf(fmaxf(v, -a), a); }
+
+struct DwtArgs {
+  const float* x;  // level-1 input (n x n)
+  float* tmp;
+  size_t tmp_stride, in_off, out_off;
+  float* s;
+  int n, m, level, levels, dirac, nw;
+  int clip;
+  float alpha;
+};
+
+__device__ __forceinline__ void put_coef(float* p, float v, int clip, float alpha) {
+  *p = clip ? clampf(*p + v, alpha) : v;
+}
+
+__global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, SaraFilters F) {
+  constexpr int RW = 2 * TO + MAX_TAPS - 2;
+  __shared__ float in[RW * RW];
+  __shared__ float lo[RW * TO], hi[RW * TO];
+  const int n = A.n, m = A.m, mo = A.m / 2;
+  const int i0 = blockIdx.y * TO, j0 = blockIdx.x * TO;
+  const int z = blockIdx.z;
+  if (z == A.nw) {  // Dirac basis at level 1: coefficient = pixel
+    for (int idx = threadIdx.x; idx < 4 * TO * TO; idx += ST) {
+      const int r = 2 * i0 + idx / (2 * TO), c = 2 * j0 + idx % (2 * TO);
+      if (r < n && c < n) put_coef(&A.s[size_t(r) * n + c], A.x[size_t(r) * n + c], A.clip, A.alpha);
+    }
+    return;
+  }
+  const int w = z;
+  const int L = F.len[w];
+  const float* src = A.level == 1 ? A.x : A.tmp + w * A.tmp_stride + A.in_off;
+  const int RE = 2 * TO + L - 2;
+  for (int idx = threadIdx.x; idx < RE * RE; idx += ST) {
+    const int ly = idx / RE, lx = idx - ly * RE;
+    const int gy = (2 * i0 + ly) % m, gx = (2 * j0 + lx) % m;
+    in[ly * RW + lx] = src[size_t(gy) * m + gx];
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < RE * TO; idx += ST) {
+    const int rho = idx / TO, j = idx - rho * TO;
+    const float* row = &in[rho * RW + 2 * j];
+    float a = 0.f, d = 0.f;
+#pragma unroll
+    for (int t = 0; t < MAX_TAPS; ++t)
+      if (t < L) {
+        a = fmaf(F.h[w][t], row[t], a);
+        d = fmaf(F.g[w][t], row[t], d);
+      }
+    lo[rho * TO + j] = a;
+    hi[rho * TO + j] = d;
+  }
+  __syncthreads();
+  float* sb = A.s + size_t(w + A.dirac) * n * n;
+  for (int idx = threadIdx.x; idx < TO * TO; idx += ST) {
+    const int i = idx / TO, j = idx - i * TO;
+    const int oi = i0 + i, oj = j0 + j;
+    if (oi >= mo || oj >= mo) continue;
+    float ll = 0.f, lh = 0.f, hl = 0.f, hh = 0.f;
+#pragma unroll
+    for (int t = 0; t < MAX_TAPS; ++t)
+      if (t < L) {
+        const float l = lo[(2 * i + t) * TO + j], h = hi[(2 * i + t) * TO + j];
+        ll = fmaf(F.h[w][t], l, ll);
+        lh = fmaf(F.h[w][t], h, lh);
+        hl = fmaf(F.g[w][t], l, hl);
+        hh = fmaf(F.g[w][t], h, hh);
+      }
+    if (A.level < A.levels) A.tmp[w * A.tmp_stride + A.out_off + size_t(oi) * mo + oj] = ll;
+    else put_coef(&sb[size_t(oi) * n + oj], ll, A.clip, A.alpha);
+    put_coef(&sb[size_t(oi) * n + mo + oj], lh, A.clip, A.alpha);
+    put_coef(&sb[size_t(mo + oi) * n + oj], hl, A.clip, A.alpha);
+    put_coef(&sb[size_t(mo + oi) * n + mo + oj], hh, A.clip, A.alpha);
+  }
+}
+
+struct IdwtArgs {
+  const float* s;
+  float* tmp;
+  size_t tmp_stride, ll_off, out_off;
+  int n, m, level, levels, dirac, nw;
+  // top level only
+  float* x;
+  const float* g;
+  float* xt;
+  float tau, sigma, varsigma;
+};
+
+// Loads the four level subbands around output tile (p0, q0) and runs the column (y)
+// synthesis into lx / hx; returns the filter length.
+template <int RS>
+__device__ __forceinline__ int synth_rows(const IdwtArgs& A, const SaraFilters& F, int w, int p0, int q0,
+                                          float (*sb)[RS * RS], float* lxs, float* hxs) {
+  const int n = A.n, mo = A.m / 2;
+  const int L = F.len[w];
+  const int RL = (TS + L) / 2;
+  const int kby = (p0 - L) / 2, kbx = (q0 - L) / 2;
+  const float* sw = A.s + size_t(w + A.dirac) * n * n;
+  const bool ll_coef = A.level == A.levels;
+  const float* ll = ll_coef ? sw : A.tmp + w * A.tmp_stride + A.ll_off;
+  const int ll_stride = ll_coef ? n : mo;
+  for (int idx = threadIdx.x; idx < 4 * RL * RL; idx += ST) {
+    const int q = idx / (RL * RL), rem = idx - q * RL * RL;
+    const int ky = rem / RL, kx = rem - ky * RL;
+    const int gy = pmod(kby + ky, mo), gx = pmod(kbx + kx, mo);
+    float v;
+    if (q == 0) v = ll[size_t(gy) * ll_stride + gx];
+    else if (q == 1) v = sw[size_t(gy) * n + mo + gx];       // low-y, high-x
+    else if (q == 2) v = sw[size_t(mo + gy) * n + gx];       // high-y, low-x
+    else v = sw[size_t(mo + gy) * n + mo + gx];              // high-y, high-x
+    sb[q][ky * RS + kx] = v;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < TS * RL; idx += ST) {
+    const int pl = idx / RL, jl = idx - pl * RL;
+    float a = 0.f, b = 0.f;
+#pragma unroll
+    for (int t = 0; t < MAX_TAPS; ++t)
+      if (t < L && ((pl - t) & 1) == 0) {
+        const int kl = (pl - t + L) >> 1;
+        a = fmaf(F.h[w][t], sb[0][kl * RS + jl], a);
+        a = fmaf(F.g[w][t], sb[2][kl * RS + jl], a);
+        b = fmaf(F.h[w][t], sb[1][kl * RS + jl], b);
+        b = fmaf(F.g[w][t], sb[3][kl * RS + jl], b);
+      }
+    lxs[pl * RS + jl] = a;
+    hxs[pl * RS + jl] = b;
+  }
+  __syncthreads();
+  return L;
+}
+
+template <int RS>
+__device__ __forceinline__ float synth_cols(const SaraFilters& F, int w, int L, int pl, int ql, const float* lxs,
+                                            const float* hxs) {
+  float o = 0.f;
+#pragma unroll
+  for (int t = 0; t < MAX_TAPS; ++t)
+    if (t < L && ((ql - t) & 1) == 0) {
+      const int jl = (ql - t + L) >> 1;
+      o = fmaf(F.h[w][t], lxs[pl * RS + jl], o);
+      o = fmaf(F.g[w][t], hxs[pl * RS + jl], o);
+    }
+  return o;
+}
+
+__global__ __launch_bounds__(ST) void k_idwt_level(IdwtArgs A, SaraFilters F) {
+  constexpr int RS = (TS + MAX_TAPS) / 2;
+  __shared__ float sb[4][RS * RS];
+  __shared__ float lxs[TS * RS], hxs[TS * RS];
+  const int w = blockIdx.z;
+  const int p0 = blockIdx.y * TS, q0 = blockIdx.x * TS, m = A.m;
+  const int L = synth_rows<RS>(A, F, w, p0, q0, sb, lxs, hxs);
+  float* out = A.tmp + w * A.tmp_stride + A.out_off;
+  for (int idx = threadIdx.x; idx < TS * TS; idx += ST) {
+    const int pl = idx / TS, ql = idx - pl * TS;
+    if (p0 + pl < m && q0 + ql < m) out[size_t(p0 + pl) * m + q0 + ql] = synth_cols<RS>(F, w, L, pl, ql, lxs, hxs);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, SaraFilters F) {
+  constexpr int RS = (TS + MAX_TAPS) / 2;
+  constexpr int PER = TS * TS / ST;
+  __shared__ float sb[4][RS * RS];
+  __shared__ float lxs[TS * RS], hxs[TS * RS];
+  const int p0 = blockIdx.y * TS, q0 = blockIdx.x * TS, n = A.n;
+  float acc[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) acc[k] = 0.f;
+  for (int w = 0; w < A.nw; ++w) {
+    const int L = synth_rows<RS>(A, F, w, p0, q0, sb, lxs, hxs);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int idx = threadIdx.x + k * ST;
+      acc[k] += synth_cols<RS>(F, w, L, idx / TS, idx % TS, lxs, hxs);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int idx = threadIdx.x + k * ST;
+    const int p = p0 + idx / TS, q = q0 + idx % TS;
+    if (p >= n || q >= n) continue;
+    const size_t o = size_t(p) * n + q;
+    const float st = acc[k] + (A.dirac ? A.s[o] : 0.f);
+    if (MODE == 0) {
+      A.x[o] = st;
+    } else {
+      const float xo = A.x[o];
+      const float xn = fmaxf(0.f, xo - A.tau * (A.sigma * st + A.varsigma * A.g[o]));
+      A.x[o] = xn;
+      A.xt[o] = 2.f * xn - xo;
+    }
+  }
+}
+
+unsigned tiles(int outputs, int t) { return unsigned((outputs + t - 1) / t); }
+
+int analysis(const Sara& S, const float* x, float* s, bool clip, float alpha, hipStream_t st) {
+  for (int lev = 1; lev <= S.levels; ++lev) {
+    const int m = S.n >> (lev - 1), mo = m / 2;
+    DwtArgs A{x, S.tmp, S.tmp_stride, lev >= 2 ? S.tmp_off[lev - 1] : 0, lev < S.levels ? S.tmp_off[lev] : 0,
+              s, S.n, m, lev, S.levels, S.dirac, S.nw, clip ? 1 : 0, alpha};
+    const int z = S.nw + ((lev == 1 && S.dirac) ? 1 : 0);
+    if (z == 0) continue;
+    hipLaunchKernelGGL(k_dwt_level, dim3(tiles(mo, TO), tiles(mo, TO), z), dim3(ST), 0, st, A, S.filt);
+    RI_LAUNCH_CHECK();
+  }
+  return RI_OK;
+}
+
+int synthesis_lower(const Sara& S, const float* s, hipStream_t st) {
+  for (int lev = S.levels; lev >= 2; --lev) {
+    const int m = S.n >> (lev - 1);
+    IdwtArgs A{s, S.tmp, S.tmp_stride, lev < S.levels ? S.tmp_off[lev] : 0, S.tmp_off[lev - 1], S.n, m, lev,
+               S.levels, S.dirac, S.nw, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f};
+    if (S.nw == 0) break;
+    hipLaunchKernelGGL(k_idwt_level, dim3(tiles(m, TS), tiles(m, TS), S.nw), dim3(ST), 0, st, A, S.filt);
+    RI_LAUNCH_CHECK();
+  }
+  return RI_OK;
+}
+
+int synthesis_top(const Sara& S, const float* s, const PrimalUpdate* u, float* x, hipStream_t st) {
+  IdwtArgs A{s, S.tmp, S.tmp_stride, S.levels > 1 ? S.tmp_off[1] : 0, 0, S.n, S.n, 1, S.levels, S.dirac, S.nw,
+             u ? u->x : x, u ? u->g : nullptr, u ? u->xt : nullptr, u ? u->tau : 0.f, u ? u->sigma : 0.f,
+             u ? u->varsigma : 0.f};
+  const dim3 g(tiles(S.n, TS), tiles(S.n, TS));
+  if (u) hipLaunchKernelGGL(k_idwt_top<1>, g, dim3(ST), 0, st, A, S.filt);
+  else hipLaunchKernelGGL(k_idwt_top<0>, g, dim3(ST), 0, st, A, S.filt);
+  RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+void destroy_sara(Sara& S) {
+  dev_free(S.tmp);
+  dev_free(S.coef_tmp);
+  dev_free(S.vec_tmp);
+  dev_free(S.dsum);
+}
+
+int create_sara(Sara& S, int n, int levels, uint32_t bases) {
+  if (bases == 0) bases = 0x1FF;
+  if (bases & ~0x1FFu) return fail(RI_EINVAL, "bases bitmask 0x%x has bits above db8", bases);
+  if (levels < 1 || levels > 6) return fail(RI_EINVAL, "levels=%d must be in [1, 6]", levels);
+  if (n < 2 || n > 4096 || (n % (1 << levels)) != 0)
+    return fail(RI_EINVAL, "n=%d must be a multiple of 2^levels=%d and at most 4096", n, 1 << levels);
+  S.n = n;
+  S.levels = levels;
+  S.dirac = (bases & 1u) ? 1 : 0;
+  S.nw = 0;
+  for (int N = 1; N <= 8; ++N) {
+    if (!(bases & (1u << N))) continue;
+    std::vector<double> h;
+    double err = 1.0;
+    daubechies_lowpass(N, h, &err);
+    if (!(err < 1e-12)) return fail(RI_EINVAL, "db%d filter orthonormality error %.3g", N, err);
+    const int w = S.nw++;
+    S.filt.len[w] = 2 * N;
+    for (int j = 0; j < 2 * N; ++j) {
+      S.filt.h[w][j] = float(h[j]);
+      S.filt.g[w][j] = float(((j & 1) ? -1.0 : 1.0) * h[2 * N - 1 - j]);
+    }
+  }
+  S.b = S.dirac + S.nw;
+  S.tmp_stride = 0;
+  for (int l = 1; l < levels; ++l) {
+    S.tmp_off[l] = S.tmp_stride;
+    S.tmp_stride += size_t(n >> l) * (n >> l);
+  }
+  RI_TRY(dev_alloc(&S.tmp, size_t(S.nw) * S.tmp_stride));
+  RI_TRY(dev_alloc(&S.coef_tmp, size_t(S.b) * n * n));
+  RI_TRY(dev_alloc(&S.vec_tmp, size_t(n) * n));
+  RI_TRY(dev_alloc(&S.dsum, SUMSQ_SCRATCH));
+  return RI_OK;
+}
+
+}  // namespace
+
+int psi_adj_apply(const Sara& S, const float* x, float* s, bool clip, float alpha, hipStream_t st) {
+  return analysis(S, x, s, clip, alpha, st);
+}
+
+int psi_apply(const Sara& S, const float* s, float* x, hipStream_t st) {
+  RI_TRY(synthesis_lower(S, s, st));
+  return synthesis_top(S, s, nullptr, x, st);
+}
+
+int psi_synth_lower(const Sara& S, const float* s, hipStream_t st) { return synthesis_lower(S, s, st); }
+
+int psi_top_update(const Sara& S, const float* s, const PrimalUpdate& u, hipStream_t st) {
+  return synthesis_top(S, s, &u, nullptr, st);
+}
+
+}  // namespace ri
+
+using ri::fail;
+
+extern "C" {
+
+int ri_sara_create(ri_sara* out, int n, int levels, uint32_t bases, hipStream_t stream) {
+  (void)stream;
+  if (!out) return fail(RI_EINVAL, "out is NULL");
+  *out = nullptr;
+  ri_sara h = new (std::nothrow) ri_sara_s;
+  if (!h) return fail(RI_ENOMEM, "host allocation failed");
+  const int rc = ri::create_sara(h->s, n, levels, bases);
+  if (rc != RI_OK) {
+    ri::destroy_sara(h->s);
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return RI_OK;
+}
+
+void ri_sara_destroy(ri_sara sara) {
+  if (!sara) return;
+  ri::destroy_sara(sara->s);
+  delete sara;
+}
+
+int ri_sara_bases(ri_sara sara, int* b) {
+  if (!sara || !b) return fail(RI_EINVAL, "NULL argument");
+  *b = sara->s.b;
+  return RI_OK;
+}
+
+int ri_psi(ri_sara sara, const float* s, float* x, hipStream_t stream) {
+  if (!sara || !s || !x) return fail(RI_EINVAL, "NULL argument");
+  return ri::psi_apply(sara->s, s, x, stream);
+}
+
+int ri_psi_adj(ri_sara sara, const float* x, float* s, hipStream_t stream) {
+  if (!sara || !s || !x) return fail(RI_EINVAL, "NULL argument");
+  return ri::psi_adj_apply(sara->s, x, s, false, 0.f, stream);
+}
+
+int ri_psi_norm(ri_sara sara, float* x0, int max_it, double rtol, double* norm_host, int* iters_host,
+                hipStream_t stream) {
+  if (!sara || !x0 || !norm_host || max_it < 1) return fail(RI_EINVAL, "bad argument");
+  ri::Sara& S = sara->s;
+  const size_t N = size_t(S.n) * S.n;
+  float* cur = x0;
+  float* nxt = S.vec_tmp;
+  double lam = 0.0, lam_prev = 0.0, sq = 0.0;
+  int it;
+  RI_TRY(ri::sumsq_f32(cur, N, S.dsum, stream));
+  RI_TRY(ri::scale_by_rsqrt(cur, N, S.dsum, stream));
+  for (it = 1; it <= max_it; ++it) {
+    RI_TRY(ri::psi_adj_apply(S, cur, S.coef_tmp, false, 0.f, stream));
+    RI_TRY(ri::psi_apply(S, S.coef_tmp, nxt, stream));
+    RI_TRY(ri::sumsq_f32(nxt, N, S.dsum, stream));
+    RI_HIP(hipMemcpyAsync(&sq, S.dsum, sizeof(double), hipMemcpyDeviceToHost, stream));
+    RI_HIP(hipStreamSynchronize(stream));
+    lam = std::sqrt(sq);
+    RI_TRY(ri::scale_by_rsqrt(nxt, N, S.dsum, stream));
+    std::swap(cur, nxt);
+    if (lam == 0.0 || std::fabs(lam - lam_prev) <= rtol * lam) break;
+    lam_prev = lam;
+  }
+  if (cur != x0) RI_HIP(hipMemcpyAsync(x0, cur, N * sizeof(float), hipMemcpyDeviceToDevice, stream));
+  RI_HIP(hipStreamSynchronize(stream));
+  *norm_host = std::sqrt(lam);
+  if (iters_host) *iters_host = it > max_it ? max_it : it;
+  return RI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,49 @@
+// Internal state of the SARA sparsity dictionary (Sec. III): Dirac plus Daubechies bases.
+#pragma once
+
+#include "common.hpp"
+
+namespace ri {
+
+constexpr int MAX_WAVELETS = 8;
+constexpr int MAX_TAPS = 16;  // db8
+
+// Filters of the wavelet bases, by wavelet slot (kernel argument, read with scalar loads).
+struct SaraFilters {
+  float h[MAX_WAVELETS][MAX_TAPS];
+  float g[MAX_WAVELETS][MAX_TAPS];
+  int len[MAX_WAVELETS];
+};
+
+struct Sara {
+  int n = 0, levels = 0;
+  int dirac = 0;  // 1 if basis 0 is the Dirac basis
+  int nw = 0;     // number of wavelet bases
+  int b = 0;      // dirac + nw
+  SaraFilters filt{};
+  size_t tmp_stride = 0;        // floats of LL scratch per wavelet
+  size_t tmp_off[8] = {0};      // offset of LL_l (l = 1..levels-1) inside a wavelet's scratch
+  float* tmp = nullptr;         // nw * tmp_stride
+  float* coef_tmp = nullptr;    // b * n * n, power iterations
+  float* vec_tmp = nullptr;     // n * n, power iterations
+  double* dsum = nullptr;
+};
+
+struct PrimalUpdate {
+  const float* g;  // Re Z^dagger F^dagger sum_i M_i^dagger v~_i
+  float* x;        // in: x^(t-1), out: x^(t)
+  float* xt;       // out: 2 x^(t) - x^(t-1)
+  float tau, sigma, varsigma;
+};
+
+// s = Psi^dagger x, or with clip: s = clip(s + Psi^dagger x, -alpha, alpha) (step 13 Moreau form).
+int psi_adj_apply(const Sara& S, const float* x, float* s, bool clip, float alpha, hipStream_t st);
+// x = Psi s.
+int psi_apply(const Sara& S, const float* s, float* x, hipStream_t st);
+// Psi s, part 1: synthesis of every level but the finest (into the dictionary's scratch).
+int psi_synth_lower(const Sara& S, const float* s, hipStream_t st);
+// Psi s, part 2, fused with steps 17-18: the finest level summed over all bases,
+// x = max(0, x - tau (sigma Psi s + varsigma g)), xt = 2 x_new - x_old.
+int psi_top_update(const Sara& S, const float* s, const PrimalUpdate& u, hipStream_t st);
+
+}  // namespace ri

@@ -1,0 +1,259 @@
+"""Python handles over the C ABI: measurement operator, SARA dictionary, PD solver state.
+
+Argument marshalling only.  Every tensor argument is checked on the host (device, dtype,
+contiguity, exact shape) before anything is enqueued; all arithmetic runs in libri.so on
+the current torch stream.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, shape, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _mask(mask, d):
+    if mask is None:
+        return None
+    return _dev(mask, torch.uint8, (d,), "mask")
+
+
+class Plan:
+    """Phi = G M F Z for an n x n image, M visibilities in d blocks (Eq. 3, Eq. 8)."""
+
+    def __init__(self, n, uv, block_off, J=8, beta=0.0, tile=0, bin=0, fft_panel=0, persistent_wgs=0):
+        lib = L.load()
+        uv = np.ascontiguousarray(uv, dtype=np.float32)
+        off = np.ascontiguousarray(block_off, dtype=np.int64)
+        if uv.ndim != 2 or uv.shape[1] != 2:
+            raise ValueError("uv must be (M, 2)")
+        self.n, self.M, self.d = int(n), int(uv.shape[0]), int(off.size - 1)
+        tune = L.Tuning(tile, bin, fft_panel, persistent_wgs)
+        h = ctypes.c_void_p()
+        L.check(lib.ri_plan_create(ctypes.byref(h), self.n, self.M, uv.ctypes.data, self.d, off.ctypes.data,
+                                   J, float(beta), ctypes.byref(tune), _stream()))
+        self._h = h
+        K, tl, ni = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        L.check(lib.ri_plan_info(h, None, None, None, ctypes.byref(K), ctypes.byref(tl), ctypes.byref(ni)))
+        self.K, self.tile, self.n_items = K.value, tl.value, ni.value
+        self.block_off = off.copy()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def order(self):
+        out = np.empty(self.M, dtype=np.int64)
+        L.check(L.load().ri_plan_order(self._h, out.ctypes.data))
+        return out
+
+    def permute(self, src, to_plan=True, out=None):
+        s = _dev(src, torch.complex64, (self.M,), "src")
+        if out is None:
+            out = torch.empty_like(src)
+        L.check(L.load().ri_plan_permute(self._h, s, _dev(out, torch.complex64, (self.M,), "out"),
+                                         1 if to_plan else 0, _stream()))
+        return out
+
+    def phi(self, x, y=None, mask=None):
+        xp = _dev(x, torch.float32, (self.n, self.n), "x")
+        if y is None:
+            y = torch.zeros(self.M, dtype=torch.complex64, device=x.device)
+        L.check(L.load().ri_phi(self._h, xp, _dev(y, torch.complex64, (self.M,), "y"), _mask(mask, self.d),
+                                _stream()))
+        return y
+
+    def phi_adj(self, y, x=None, mask=None):
+        yp = _dev(y, torch.complex64, (self.M,), "y")
+        if x is None:
+            x = torch.empty(self.n, self.n, dtype=torch.float32, device=y.device)
+        L.check(L.load().ri_phi_adj(self._h, yp, _dev(x, torch.float32, (self.n, self.n), "x"),
+                                    _mask(mask, self.d), _stream()))
+        return x
+
+    def block_sumsq(self, y, out=None):
+        """||y_i||^2 per block in FP64 (device)."""
+        yp = _dev(y, torch.complex64, (self.M,), "y")
+        if out is None:
+            out = torch.empty(self.d, dtype=torch.float64, device=y.device)
+        L.check(L.load().ri_block_sumsq(self._h, yp, _dev(out, torch.float64, (self.d,), "out"), _stream()))
+        return out
+
+    def norm(self, x0, max_it=1000, rtol=1e-7):
+        """||Phi||_S by power iteration from x0 (overwritten)."""
+        v, it = ctypes.c_double(), ctypes.c_int()
+        L.check(L.load().ri_phi_norm(self._h, _dev(x0, torch.float32, (self.n, self.n), "x0"), int(max_it),
+                                     float(rtol), ctypes.byref(v), ctypes.byref(it), _stream()))
+        return v.value, it.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().ri_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Sara:
+    """Psi: Dirac + db1..db8, `levels`-level periodic 2D DWTs (Sec. III)."""
+
+    def __init__(self, n, levels=4, bases=0):
+        lib = L.load()
+        h = ctypes.c_void_p()
+        L.check(lib.ri_sara_create(ctypes.byref(h), int(n), int(levels), int(bases), _stream()))
+        self._h = h
+        b = ctypes.c_int()
+        L.check(lib.ri_sara_bases(h, ctypes.byref(b)))
+        self.n, self.levels, self.b = int(n), int(levels), b.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def psi(self, s, x=None):
+        sp = _dev(s, torch.float32, (self.b, self.n, self.n), "s")
+        if x is None:
+            x = torch.empty(self.n, self.n, dtype=torch.float32, device=s.device)
+        L.check(L.load().ri_psi(self._h, sp, _dev(x, torch.float32, (self.n, self.n), "x"), _stream()))
+        return x
+
+    def psi_adj(self, x, s=None):
+        xp = _dev(x, torch.float32, (self.n, self.n), "x")
+        if s is None:
+            s = torch.empty(self.b, self.n, self.n, dtype=torch.float32, device=x.device)
+        L.check(L.load().ri_psi_adj(self._h, xp, _dev(s, torch.float32, (self.b, self.n, self.n), "s"),
+                                    _stream()))
+        return s
+
+    def norm(self, x0, max_it=1000, rtol=1e-7):
+        v, it = ctypes.c_double(), ctypes.c_int()
+        L.check(L.load().ri_psi_norm(self._h, _dev(x0, torch.float32, (self.n, self.n), "x0"), int(max_it),
+                                     float(rtol), ctypes.byref(v), ctypes.byref(it), _stream()))
+        return v.value, it.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().ri_sara_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PD:
+    """State of Algorithm 1 on the GPU (x, x~, s, v and the running sum of v~)."""
+
+    def __init__(self, plan: Plan, sara: Sara, y, eps, tau, sigma, varsigma, kappa, psi_norm, phi_norm):
+        lib = L.load()
+        self.plan, self.sara = plan, sara
+        yp = _dev(y, torch.complex64, (plan.M,), "y")
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        if eps.shape != (plan.d,):
+            raise ValueError("eps must have one radius per block")
+        prm = L.PDParams(tau, sigma, varsigma, kappa, psi_norm, phi_norm)
+        h = ctypes.c_void_p()
+        L.check(lib.ri_pd_create(ctypes.byref(h), plan.handle, sara.handle, yp, eps.ctypes.data,
+                                 ctypes.byref(prm), _stream()))
+        self._h = h
+        self.eps = eps
+        self.params = dict(tau=tau, sigma=sigma, varsigma=varsigma, kappa=kappa, psi_norm=psi_norm,
+                           phi_norm=phi_norm)
+
+    def step(self, mask=None, stats=None):
+        st = None if stats is None else _dev(stats, torch.float64, (self.plan.d, 2), "stats")
+        L.check(L.load().ri_pd_step(self._h, _mask(mask, self.plan.d), st, _stream()))
+
+    def step_plain(self, mask_host=None, stats=None):
+        mh = None
+        if mask_host is not None:
+            mh = np.ascontiguousarray(mask_host, dtype=np.uint8)
+            if mh.shape != (self.plan.d,):
+                raise ValueError("mask_host must have d entries")
+        st = None if stats is None else _dev(stats, torch.float64, (self.plan.d, 2), "stats")
+        L.check(L.load().ri_pd_step_plain(self._h, None if mh is None else mh.ctypes.data, st, _stream()))
+
+    def refresh(self):
+        L.check(L.load().ri_pd_refresh(self._h, _stream()))
+
+    def _shape(self, which):
+        n = self.plan.n
+        return {L.RI_PD_X: ((n, n), torch.float32), L.RI_PD_XTILDE: ((n, n), torch.float32),
+                L.RI_PD_S: ((self.sara.b, n, n), torch.float32),
+                L.RI_PD_V: ((self.plan.M,), torch.complex64)}[which]
+
+    def get(self, which, out=None):
+        shape, dt = self._shape(which)
+        if out is None:
+            out = torch.empty(shape, dtype=dt, device="cuda")
+        p = _dev(out, dt, shape, "out")
+        L.check(L.load().ri_pd_get(self._h, which, p, out.numel() * out.element_size(), _stream()))
+        return out
+
+    def set(self, which, value):
+        shape, dt = self._shape(which)
+        p = _dev(value, dt, shape, "value")
+        L.check(L.load().ri_pd_set(self._h, which, p, value.numel() * value.element_size(), _stream()))
+
+    @property
+    def iteration(self):
+        v = ctypes.c_int64()
+        L.check(L.load().ri_pd_get(self._h, L.RI_PD_ITER, ctypes.byref(v), 8, None))
+        return v.value
+
+    @iteration.setter
+    def iteration(self, t):
+        v = ctypes.c_int64(int(t))
+        L.check(L.load().ri_pd_set(self._h, L.RI_PD_ITER, ctypes.byref(v), 8, None))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.load().ri_pd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def residual_energy(resid_norm, eps):
+    """Eq. 13 (host, in the library)."""
+    r = np.ascontiguousarray(resid_norm, dtype=np.float64)
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    out = np.empty_like(r)
+    L.check(L.load().ri_residual_energy(r.ctypes.data, e.ctypes.data, r.size, out.ctypes.data))
+    return out
+
+
+def probabilities(c, n_nodes, p_min, p_max):
+    """Eq. 14 (host, in the library).  Returns (p, a)."""
+    c = np.ascontiguousarray(c, dtype=np.float64)
+    p = np.empty_like(c)
+    a = ctypes.c_double()
+    L.check(L.load().ri_probs(c.ctypes.data, c.size, float(n_nodes), float(p_min), float(p_max), p.ctypes.data,
+                              ctypes.byref(a)))
+    return p, a.value

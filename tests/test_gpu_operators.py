@@ -1,0 +1,174 @@
+"""GPU parity of the operators behind the C ABI (Phi, Phi^dagger, Psi, Psi^dagger, norms)
+against the FP64 oracle, at sizes spanning several tiles and ragged blocks.
+
+Tolerance: relative l2 <= 1e-5 per operator output (FP32 arithmetic against FP64)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from helpers import problem, rel_l2, to_plan, to_user
+from oracle.measurement import Measurement
+from oracle.power import phi_norm as oracle_phi_norm
+from oracle.wavelets import Sara as OSara
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_1610_08895_amd as R
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return R
+
+
+def test_library_shares_torchs_hip_runtime(R):
+    from paper_1610_08895_amd import _lib
+
+    lib = _lib.load()
+    torch.zeros(1, device="cuda")
+    maps = open("/proc/self/maps").read()
+    hip_libs = {l.split()[-1] for l in maps.splitlines() if "libamdhip64" in l}
+    assert len(hip_libs) == 1, hip_libs
+    assert any(l.endswith("libri.so") for l in maps.split())
+    import ctypes
+
+    v = ctypes.c_int()
+    _lib.check(lib.ri_hip_runtime_version(ctypes.byref(v)))
+    assert v.value > 0
+
+
+CASES = [
+    # n, M, d, scheme
+    (64, 8192, 4, "equal"),
+    (32, 1000, 3, "lognormal_small"),
+    (128, 30000, 7, "annuli"),
+    (16, 257, 2, "equal"),
+]
+
+
+def _case(n, M, d, scheme, seed=1):
+    if scheme == "lognormal_small":
+        x, uv, off = problem(n, M, 1, "equal", seed)
+        off = np.array([0, 1, 400, M])            # ragged: a one-visibility block
+        return x, uv, off
+    return problem(n, M, d, scheme, seed)
+
+
+@pytest.mark.parametrize("n,M,d,scheme", CASES)
+def test_phi_and_adjoint_match_oracle(R, n, M, d, scheme):
+    x, uv, off = _case(n, M, d, scheme)
+    plan = R.Plan(n, uv, off)
+    order = plan.order()
+    meas = Measurement(uv, off, (n, n))
+    y_ref = meas.phi(x)
+    y = plan.phi(torch.tensor(x, dtype=torch.float32, device="cuda"))
+    y_user = to_user(y.cpu().numpy(), order)
+    assert rel_l2(y_user, y_ref) < TOL
+    rng = np.random.default_rng(5)
+    w = (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    xa_ref = meas.phi_adj_real(w)
+    xa = plan.phi_adj(torch.tensor(to_plan(w, order), dtype=torch.complex64, device="cuda"))
+    assert rel_l2(xa.cpu().numpy(), xa_ref) < TOL
+
+
+def test_phi_masks_touch_only_active_blocks(R):
+    n, M, d = 64, 6000, 5
+    x, uv, off = problem(n, M, d, "equal", 3)
+    plan = R.Plan(n, uv, off)
+    order = plan.order()
+    meas = Measurement(uv, off, (n, n))
+    mask = np.array([1, 0, 1, 0, 0], np.uint8)
+    y = torch.full((M,), 7 + 7j, dtype=torch.complex64, device="cuda")
+    plan.phi(torch.tensor(x, dtype=torch.float32, device="cuda"), y,
+             mask=torch.tensor(mask, device="cuda"))
+    yp = y.cpu().numpy()
+    y_ref = to_plan(meas.phi(x), order)
+    for i in range(d):
+        sl = slice(off[i], off[i + 1])
+        if mask[i]:
+            assert rel_l2(yp[sl], y_ref[sl]) < TOL
+        else:
+            assert np.all(yp[sl] == 7 + 7j)
+    w = np.random.default_rng(1).standard_normal(M) + 0j
+    xa = plan.phi_adj(torch.tensor(to_plan(w, order), dtype=torch.complex64, device="cuda"),
+                      mask=torch.tensor(mask, device="cuda"))
+    ref = meas.phi_adj_real(w, blocks=np.flatnonzero(mask))
+    assert rel_l2(xa.cpu().numpy(), ref) < TOL
+    # empty active set: the adjoint is exactly zero
+    xz = plan.phi_adj(torch.tensor(to_plan(w, order), dtype=torch.complex64, device="cuda"),
+                      mask=torch.zeros(d, dtype=torch.uint8, device="cuda"))
+    assert torch.count_nonzero(xz).item() == 0
+
+
+def test_gpu_adjoint_dot_product(R):
+    n, M, d = 128, 40000, 8
+    x, uv, off = problem(n, M, d, "lognormal", 4)
+    plan = R.Plan(n, uv, off)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    xv = torch.randn(n, n, generator=g).cuda()
+    yv = torch.randn(M, dtype=torch.complex64, generator=g).cuda()
+    lhs = torch.vdot(yv.to(torch.complex128), plan.phi(xv).to(torch.complex128)).real.item()
+    rhs = torch.dot(plan.phi_adj(yv).double().flatten(), xv.double().flatten()).item()
+    assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+
+
+@pytest.mark.parametrize("n,levels", [(64, 4), (32, 4), (128, 3), (16, 1)])
+def test_psi_and_adjoint_match_oracle(R, n, levels):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal((n, n))
+    sara = R.Sara(n, levels)
+    ref = OSara(n, levels)
+    s = sara.psi_adj(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+    s_ref = ref.adj(x)
+    assert s.shape == s_ref.shape == (9, n, n)
+    for b in range(9):
+        assert rel_l2(s[b], s_ref[b]) < TOL, b
+    c = rng.standard_normal((9, n, n))
+    xs = sara.psi(torch.tensor(c, dtype=torch.float32, device="cuda")).cpu().numpy()
+    assert rel_l2(xs, ref.fwd(c)) < TOL
+    # Psi Psi^dagger = 9 I
+    xx = sara.psi(sara.psi_adj(torch.tensor(x, dtype=torch.float32, device="cuda"))).cpu().numpy()
+    assert rel_l2(xx, 9 * x) < TOL
+
+
+def test_psi_subsets_of_bases(R):
+    n = 64
+    x = np.random.default_rng(2).standard_normal((n, n))
+    for bases, wl in [(0b10, (1,)), (0b100000001, (8,)), (0b1, ())]:
+        sara = R.Sara(n, 4, bases)
+        ref = OSara(n, 4, wavelets=wl, dirac=bool(bases & 1))
+        s = sara.psi_adj(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy()
+        assert rel_l2(s, ref.adj(x)) < TOL
+
+
+def test_operator_norms(R):
+    n, M, d = 64, 8192, 4
+    x, uv, off = problem(n, M, d, "equal", 6)
+    plan = R.Plan(n, uv, off)
+    x0 = synth.power_start(n, 11)
+    # the spectral gap is small here, so both sides run the same fixed number of iterations
+    ref, _ = oracle_phi_norm(Measurement(uv, off, (n, n)), x0, tol=0.0, max_it=300)
+    v, it = plan.norm(torch.tensor(x0, dtype=torch.float32, device="cuda"), max_it=300, rtol=0.0)
+    assert it == 300
+    assert v == pytest.approx(ref, rel=1e-5)
+    sara = R.Sara(n, 4)
+    pv, _ = sara.norm(torch.tensor(x0, dtype=torch.float32, device="cuda"), max_it=200, rtol=1e-9)
+    assert pv == pytest.approx(3.0, rel=1e-5)
+
+
+def test_bad_arguments_raise(R):
+    from paper_1610_08895_amd._lib import RIError
+
+    uv = np.zeros((10, 2), np.float32)
+    with pytest.raises(RIError):
+        R.Plan(48, uv, [0, 10])                         # not a power of two
+    with pytest.raises(RIError):
+        R.Plan(64, uv, [0, 5, 5, 10])                   # empty block
+    with pytest.raises(RIError):
+        R.Sara(40, 4)                                   # not divisible by 16
+    plan = R.Plan(64, uv, [0, 10])
+    with pytest.raises(ValueError):
+        plan.phi(torch.zeros(32, 32, device="cuda"))    # wrong image shape (host check)

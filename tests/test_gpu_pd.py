@@ -1,0 +1,196 @@
+"""GPU parity of Algorithm 1 (ri_pd_step, ri_pd_step_plain) against the FP64 oracle.
+
+Per-iteration states agree to FP32 rounding (relative l2 <= 1e-4 over a few tens of
+iterations); the reconstruction SNR after a full run agrees within 0.05 dB."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from helpers import problem, rel_l2, to_plan, to_user
+from oracle import pd as opd
+from oracle.measurement import Measurement
+from oracle.metrics import snr
+from oracle.power import phi_norm as oracle_phi_norm
+from oracle.wavelets import Sara as OSara
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_1610_08895_amd as R
+
+    assert torch.cuda.is_available()
+    return R
+
+
+def _setup(R, n=64, M=8192, d=4, scheme="equal", seed=2, isnr=30.0, blobs=5, points=10):
+    x, uv, off = problem(n, M, d, scheme, seed, blobs, points)
+    meas = Measurement(uv, off, (n, n))
+    osara = OSara(n)
+    y0 = meas.phi(x)
+    sig = synth.noise_sigma(y0, isnr)
+    y = y0 + synth.complex_noise(M, sig, np.random.default_rng(seed + 100))
+    eps = synth.l2_ball_radii(off, sig)
+    phin, _ = oracle_phi_norm(meas, synth.power_start(n, seed), tol=0.0, max_it=100)
+    prm = opd.default_params(3.0, phin)
+    plan = R.Plan(n, uv, off)
+    order = plan.order()
+    sara = R.Sara(n)
+    y_plan = torch.tensor(to_plan(y, order), dtype=torch.complex64, device="cuda")
+    return dict(x=x, uv=uv, off=off, meas=meas, osara=osara, y=y, eps=eps, phin=phin, prm=prm, plan=plan,
+                order=order, sara=sara, y_plan=y_plan)
+
+
+def _pd(R, S):
+    p = S["prm"]
+    return R.PD(S["plan"], S["sara"], S["y_plan"], S["eps"], p.tau, p.sigma, p.varsigma, p.kappa, 3.0, S["phin"])
+
+
+def _v_user(pdg, S):
+    return to_user(pdg.get(3).cpu().numpy(), S["order"])
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_iterations_match_oracle_with_random_masks(R, plain):
+    S = _setup(R, n=64, M=6000, d=5, scheme="lognormal", seed=3)
+    pdg = _pd(R, S)
+    meas, osara = S["meas"], S["osara"]
+    yb = opd.split_blocks(meas, S["y"])
+    st = opd.init_state(meas, osara)
+    rng = np.random.default_rng(4)
+    stats = torch.zeros(5, 2, dtype=torch.float64, device="cuda")
+    for t in range(15):
+        mask = (rng.uniform(size=5) < 0.6).astype(np.uint8)
+        if t == 0:
+            mask[:] = 1
+        if t == 7:
+            mask[:] = 0          # empty active set
+        ost = opd.iteration(meas, osara, yb, S["eps"], S["prm"], st, mask.astype(bool))
+        if plain:
+            pdg.step_plain(mask, stats)
+        else:
+            pdg.step(torch.tensor(mask, device="cuda"), stats)
+        gst = np.sqrt(stats.cpu().numpy())
+        for i in range(5):
+            if mask[i]:
+                assert gst[i] == pytest.approx(ost[i], rel=1e-4), (t, i)
+            else:
+                assert np.isnan(gst[i]).all()
+        x = pdg.get(0).cpu().numpy()
+        assert rel_l2(x, st.x) < 1e-4 * (1 + t), t
+        assert rel_l2(pdg.get(1).cpu().numpy(), st.xt) < 1e-4 * (1 + t)
+        assert rel_l2(pdg.get(2).cpu().numpy(), st.s) < 1e-4 * (1 + t)
+        vg = _v_user(pdg, S)
+        vo = np.concatenate(st.v)
+        if np.linalg.norm(vo) > 0:
+            assert rel_l2(vg, vo) < 1e-4 * (1 + t)
+
+
+def test_inactive_blocks_keep_their_duals_bitwise(R):
+    S = _setup(R, n=64, M=6000, d=4, seed=5)
+    pdg = _pd(R, S)
+    for _ in range(3):
+        pdg.step()
+    v0 = pdg.get(3).cpu().numpy()
+    mask = np.array([0, 1, 0, 1], np.uint8)
+    pdg.step(torch.tensor(mask, device="cuda"))
+    v1 = pdg.get(3).cpu().numpy()
+    off = S["off"]
+    for i in (0, 2):
+        assert np.array_equal(v0[off[i]:off[i + 1]], v1[off[i]:off[i + 1]])
+
+
+def test_batched_equals_plain(R):
+    S = _setup(R, n=64, M=8192, d=6, scheme="lognormal", seed=6)
+    a, b = _pd(R, S), _pd(R, S)
+    rng = np.random.default_rng(0)
+    for _ in range(12):
+        mask = (rng.uniform(size=6) < 0.7).astype(np.uint8)
+        a.step(torch.tensor(mask, device="cuda"))
+        b.step_plain(mask)
+    assert rel_l2(a.get(0).cpu().numpy(), b.get(0).cpu().numpy()) < 1e-5
+    assert rel_l2(a.get(3).cpu().numpy(), b.get(3).cpu().numpy()) < 1e-5
+
+
+def test_snr_parity_small_workload(R):
+    """The smallest workload (64x64, M = 8192, 4 blocks, p = 1, 200 iterations)."""
+    w = synth.WORKLOADS["n64_m8k_d4"]
+    inp = synth.make_inputs(w)
+    meas = Measurement(inp.uv, inp.block_off, (w.n, w.n))
+    y, sig, eps = synth.add_noise(w, meas.phi(inp.x_true), inp.block_off)
+    phin, _ = oracle_phi_norm(meas, synth.power_start(w.n, w.seed(synth.SEED_POWER)), tol=0.0, max_it=100)
+    prm = opd.default_params(3.0, phin)
+    T = w.iterations
+    st, hist = opd.run(meas, OSara(w.n), y, eps, prm, np.ones((T, w.d), bool), x_true=inp.x_true)
+    plan = R.Plan(w.n, inp.uv, inp.block_off)
+    order = plan.order()
+    from paper_1610_08895_amd.solver import Solver
+
+    sol = Solver(plan, R.Sara(w.n), torch.tensor(to_plan(y, order), dtype=torch.complex64, device="cuda"),
+                 eps, 3.0, phin)
+    sol.run(T, refresh=64)
+    s_gpu, s_ref = snr(inp.x_true, sol.x()), hist[-1]["snr"]
+    print(f"SNR oracle {s_ref:.4f} dB, GPU {s_gpu:.4f} dB")
+    assert s_ref > 15.0
+    assert abs(s_gpu - s_ref) <= 0.05
+
+
+def test_adaptive_run_replays_oracle_masks(R):
+    """Eq. 14 schedule (annuli blocks): GPU driven with the oracle's mask log."""
+    S = _setup(R, n=64, M=12000, d=8, scheme="annuli", seed=8, isnr=20.0)
+    T = 120
+    u = synth.activity_uniforms(T, S["plan"].d, 99)
+    st, hist, masks, probs = opd.run_adaptive(S["meas"], S["osara"], S["y"], S["eps"], S["prm"], u,
+                                              n_nodes=3.0, p_min=0.05, p_max=0.8, x_true=S["x"])
+    assert 0 < masks.sum() < masks.size
+    from paper_1610_08895_amd.solver import Solver
+
+    sol = Solver(S["plan"], S["sara"], S["y_plan"], S["eps"], 3.0, S["phin"])
+    sol.run(T, masks=masks, refresh=32)
+    assert abs(snr(S["x"], sol.x()) - hist[-1]["snr"]) <= 0.05
+    # the first iteration's probabilities from Eq. 13 at x = 0 match the oracle's
+    from paper_1610_08895_amd.solver import Schedule
+
+    sol2 = Solver(S["plan"], S["sara"], S["y_plan"], S["eps"], 3.0, S["phin"])
+    h2 = sol2.run(1, Schedule("adaptive", n_nodes=3.0, p_min=0.05, p_max=0.8), uniforms=u)
+    assert np.allclose(h2["p"][0], probs[0], rtol=1e-6, atol=1e-9)
+
+
+def test_refresh_and_checkpoint_resume(R):
+    S = _setup(R, n=64, M=8192, d=4, seed=9)
+    a = _pd(R, S)
+    for _ in range(20):
+        a.step()
+    x_before = a.get(0).clone()
+    a.refresh()
+    saved = [a.get(w).clone() for w in (0, 1, 2, 3)]
+    for _ in range(5):
+        a.step()
+    b = _pd(R, S)
+    for w, v in zip((0, 1, 2, 3), saved):
+        b.set(w, v)
+    b.iteration = 20
+    for _ in range(5):
+        b.step()
+    assert b.iteration == 25 == a.iteration
+    assert rel_l2(a.get(0).cpu().numpy(), b.get(0).cpu().numpy()) < 1e-5
+    assert torch.equal(saved[0], x_before)
+
+
+def test_graph_replay_matches_eager(R):
+    from paper_1610_08895_amd.solver import Solver
+
+    S = _setup(R, n=64, M=8192, d=5, scheme="lognormal", seed=10)
+    eager = Solver(S["plan"], S["sara"], S["y_plan"], S["eps"], 3.0, S["phin"])
+    plan2 = R.Plan(64, S["uv"], S["off"])          # the graph baked in plan buffers of its own
+    graph = Solver(plan2, R.Sara(64), S["y_plan"], S["eps"], 3.0, S["phin"])
+    rng = np.random.default_rng(1)
+    for t in range(8):
+        mask = (rng.uniform(size=5) < 0.6).astype(np.uint8)
+        eager.step(mask)
+        graph.step(mask, graph=True)
+        torch.cuda.synchronize()
+        assert rel_l2(graph.x(), eager.x()) < 1e-5, t
+        assert torch.allclose(graph.stats_dev.nan_to_num(-1), eager.stats_dev.nan_to_num(-1), rtol=1e-5)
