@@ -7,7 +7,9 @@ import synth
 def rel_l2(a, b):
     a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) or np.iscomplexobj(b) else np.float64)
     b = np.asarray(b, dtype=a.dtype)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    nb = np.linalg.norm(b)
+    # a zero reference (e.g. duals at the first iteration) compares in absolute terms
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
 
 
 def problem(n, M, d, scheme="equal", seed=0, blobs=5, points=10, outliers=0.0):
