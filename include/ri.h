@@ -185,6 +185,30 @@ int ri_pd_step_plain(ri_pd pd, const uint8_t* mask_host, double* stats, hipStrea
  * the accumulated rounding.  Enqueue-only (graph-capturable). */
 int ri_pd_refresh(ri_pd pd, hipStream_t stream);
 
+/* Stages of one iteration, for per-stage timing. */
+enum {
+  RI_STAGE_ACTIVE = 0,    /* active-set work list (step 3)                          */
+  RI_STAGE_FFT_ROWS = 1,  /* F Z x~, row pass (step 4)                               */
+  RI_STAGE_FFT_COLS = 2,  /* F Z x~, column pass (step 4)                            */
+  RI_STAGE_DEGRID = 3,    /* G_i b_i, residuals, FP64 block norms (steps 5, 8)       */
+  RI_STAGE_GRID = 4,      /* l2-ball shrink, G_i^dagger update (steps 8, 9, 11)      */
+  RI_STAGE_IFFT_COLS = 5, /* Z^dagger F^dagger, column pass (step 17)                */
+  RI_STAGE_IFFT_ROWS = 6, /* Z^dagger F^dagger, row pass (step 17)                   */
+  RI_STAGE_STATS = 7,     /* export of the block statistics                         */
+  RI_STAGE_PSI_ADJ = 8,   /* Psi^dagger x~ and dual clip, all levels (step 13)       */
+  RI_STAGE_PSI_SYNTH = 9, /* Psi s, every level but the finest (step 14)             */
+  RI_STAGE_UPDATE = 10,   /* finest level of Psi s + steps 17-18                    */
+  RI_STAGE_COUNT = 11
+};
+
+/* Enable (1) or disable (0) per-stage timing: while enabled, each ri_pd_step /
+ * ri_pd_step_plain outside graph capture records a HIP event pair around every stage
+ * on the stream that stage runs on.  Clears earlier records. */
+int ri_pd_timing(ri_pd pd, int enable);
+/* Sum of the recorded durations (ms) and the number of records per stage, for the first
+ * n stages; waits for the recorded events, then clears the records (host outputs). */
+int ri_pd_stage_times(ri_pd pd, double* total_ms, int* launches, int n);
+
 /* State access for checkpoint / resume and inspection.  which: */
 enum {
   RI_PD_X = 0,     /* n*n float32                                   */

@@ -95,12 +95,17 @@ __global__ __launch_bounds__(NT) void k_adj_rows(const float2* __restrict__ rows
 }
 
 template <int K>
-int fwd_impl(const Plan& p, const float* x, float2* grid, hipStream_t s) {
+int fwd_rows_impl(const Plan& p, const float* x, float2*, hipStream_t s) {
   using RC = RowCfg<K>;
-  using CC = ColCfg<K>;
   hipLaunchKernelGGL((k_fwd_rows<K, RC::W, RC::NT>), dim3(K / 2 / RC::W), dim3(RC::NT), 0, s, x, p.scale,
                      p.rowbuf, p.twiddle);
   RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+template <int K>
+int fwd_cols_impl(const Plan& p, const float*, float2* grid, hipStream_t s) {
+  using CC = ColCfg<K>;
   hipLaunchKernelGGL((k_fwd_cols<K, CC::W, CC::NT>), dim3(K / CC::W), dim3(CC::NT), 0, s, p.rowbuf, grid,
                      p.twiddle);
   RI_LAUNCH_CHECK();
@@ -108,12 +113,17 @@ int fwd_impl(const Plan& p, const float* x, float2* grid, hipStream_t s) {
 }
 
 template <int K>
-int adj_impl(const Plan& p, const float2* grid, float* x, hipStream_t s) {
-  using RC = RowCfg<K>;
+int adj_cols_impl(const Plan& p, const float2* grid, float*, hipStream_t s) {
   using CC = ColCfg<K>;
   hipLaunchKernelGGL((k_adj_cols<K, CC::W, CC::NT>), dim3(K / CC::W), dim3(CC::NT), 0, s, grid, p.rowbuf,
                      p.twiddle);
   RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+template <int K>
+int adj_rows_impl(const Plan& p, const float2*, float* x, hipStream_t s) {
+  using RC = RowCfg<K>;
   hipLaunchKernelGGL((k_adj_rows<K, RC::W, RC::NT>), dim3(K / 2 / RC::W), dim3(RC::NT), 0, s, p.rowbuf,
                      p.scale, x, p.twiddle);
   RI_LAUNCH_CHECK();
@@ -135,12 +145,30 @@ int adj_impl(const Plan& p, const float2* grid, float* x, hipStream_t s) {
     default: return fail(RI_EINVAL, "unsupported FFT size K=%d", p.K);    \
   }
 
+int fft_forward_rows(const Plan& p, const float* x, hipStream_t s) {
+  RI_FFT_DISPATCH(fwd_rows_impl, p, x, nullptr, s)
+}
+
+int fft_forward_cols(const Plan& p, float2* grid, hipStream_t s) {
+  RI_FFT_DISPATCH(fwd_cols_impl, p, nullptr, grid, s)
+}
+
+int fft_adjoint_cols(const Plan& p, const float2* grid, hipStream_t s) {
+  RI_FFT_DISPATCH(adj_cols_impl, p, grid, nullptr, s)
+}
+
+int fft_adjoint_rows(const Plan& p, float* x, hipStream_t s) {
+  RI_FFT_DISPATCH(adj_rows_impl, p, nullptr, x, s)
+}
+
 int fft_forward(const Plan& p, const float* x, float2* grid, hipStream_t s) {
-  RI_FFT_DISPATCH(fwd_impl, p, x, grid, s)
+  RI_TRY(fft_forward_rows(p, x, s));
+  return fft_forward_cols(p, grid, s);
 }
 
 int fft_adjoint(const Plan& p, const float2* grid, float* x, hipStream_t s) {
-  RI_FFT_DISPATCH(adj_impl, p, grid, x, s)
+  RI_TRY(fft_adjoint_cols(p, grid, s));
+  return fft_adjoint_rows(p, x, s);
 }
 
 }  // namespace ri

@@ -39,6 +39,15 @@ struct ri_pd_s {
   int64_t iter = 0;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // optional per-stage timing: an event pair around each stage, on the stage's stream
+  bool timing = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  int open[RI_STAGE_COUNT] = {};
 };
 
 namespace ri {
@@ -52,6 +61,45 @@ __global__ void k_export_stats(const uint8_t* __restrict__ mask, const double* _
     out[2 * i + 1] = act ? in[2 * i + 1] : __builtin_nan("");
   }
 }
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+int take_event(ri_pd_s* P, hipEvent_t* e) {
+  if (!P->pool.empty()) {
+    *e = P->pool.back();
+    P->pool.pop_back();
+    return RI_OK;
+  }
+  RI_HIP(hipEventCreate(e));
+  return RI_OK;
+}
+
+int stage_begin(ri_pd_s* P, int st, hipStream_t s) {
+  if (!P->timing || capturing(s)) return RI_OK;
+  ri_pd_s::Rec r{st, nullptr, nullptr};
+  RI_TRY(take_event(P, &r.a));
+  RI_TRY(take_event(P, &r.b));
+  RI_HIP(hipEventRecord(r.a, s));
+  P->open[st] = int(P->recs.size());
+  P->recs.push_back(r);
+  return RI_OK;
+}
+
+int stage_end(ri_pd_s* P, int st, hipStream_t s) {
+  if (!P->timing || capturing(s)) return RI_OK;
+  RI_HIP(hipEventRecord(P->recs[P->open[st]].b, s));
+  return RI_OK;
+}
+
+#define RI_STAGE(P, ST, S, CALL)       \
+  do {                                \
+    RI_TRY(ri::stage_begin(P, ST, S)); \
+    RI_TRY(CALL);                     \
+    RI_TRY(ri::stage_end(P, ST, S));   \
+  } while (0)
 
 void destroy_pd(ri_pd_s* P) {
   dev_free(P->y);
@@ -68,6 +116,11 @@ void destroy_pd(ri_pd_s* P) {
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   if (P->side) (void)hipStreamDestroy(P->side);
+  for (auto& r : P->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : P->pool) (void)hipEventDestroy(e);
 }
 
 int refresh_sum(ri_pd_s* P, hipStream_t s) {
@@ -86,13 +139,15 @@ int export_stats(ri_pd_s* P, const uint8_t* mask, double* stats, hipStream_t s) 
 
 int sparsity_branch(ri_pd_s* P, hipStream_t s) {
   // step 13 (Moreau form of the soft-threshold), then Psi s below the finest level
-  RI_TRY(psi_adj_apply(*P->sara, P->xt, P->s, true, P->alpha, s));
-  return psi_synth_lower(*P->sara, P->s, s);
+  RI_STAGE(P, RI_STAGE_PSI_ADJ, s, psi_adj_apply(*P->sara, P->xt, P->s, true, P->alpha, s));
+  RI_STAGE(P, RI_STAGE_PSI_SYNTH, s, psi_synth_lower(*P->sara, P->s, s));
+  return RI_OK;
 }
 
 int primal_update(ri_pd_s* P, hipStream_t s) {
   PrimalUpdate u{P->g, P->x, P->xt, float(P->prm.tau), float(P->prm.sigma), float(P->prm.varsigma)};
-  return psi_top_update(*P->sara, P->s, u, s);
+  RI_STAGE(P, RI_STAGE_UPDATE, s, psi_top_update(*P->sara, P->s, u, s));
+  return RI_OK;
 }
 
 }  // namespace
@@ -181,12 +236,16 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
   RI_TRY(ri::sparsity_branch(P, P->side));
   RI_HIP(hipEventRecord(P->ev_join, P->side));
   // data-fidelity branch
-  RI_TRY(ri::build_active(p, mask, P->stats, stream));
-  RI_TRY(ri::fft_forward(p, P->xt, p.grid, stream));
-  RI_TRY(ri::degrid_residual(p, p.grid, P->y, P->v, P->e, P->stats, p.active_list, p.active_count, 0, 0, stream));
-  RI_TRY(ri::grid_project(p, P->e, P->v, P->stats, P->eps, P->sum, p.active_list, p.active_count, 0, 0, stream));
-  RI_TRY(ri::fft_adjoint(p, P->sum, P->g, stream));
-  RI_TRY(ri::export_stats(P, mask, stats, stream));
+  RI_STAGE(P, RI_STAGE_ACTIVE, stream, ri::build_active(p, mask, P->stats, stream));
+  RI_STAGE(P, RI_STAGE_FFT_ROWS, stream, ri::fft_forward_rows(p, P->xt, stream));
+  RI_STAGE(P, RI_STAGE_FFT_COLS, stream, ri::fft_forward_cols(p, p.grid, stream));
+  RI_STAGE(P, RI_STAGE_DEGRID, stream,
+           ri::degrid_residual(p, p.grid, P->y, P->v, P->e, P->stats, p.active_list, p.active_count, 0, 0, stream));
+  RI_STAGE(P, RI_STAGE_GRID, stream,
+           ri::grid_project(p, P->e, P->v, P->stats, P->eps, P->sum, p.active_list, p.active_count, 0, 0, stream));
+  RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
+  RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows(p, P->g, stream));
+  RI_STAGE(P, RI_STAGE_STATS, stream, ri::export_stats(P, mask, stats, stream));
   // join, then Psi s and the primal update
   RI_HIP(hipStreamWaitEvent(stream, P->ev_join, 0));
   RI_TRY(ri::primal_update(P, stream));
@@ -203,23 +262,62 @@ int ri_pd_step_plain(ri_pd P, const uint8_t* mask_host, double* stats, hipStream
     mask_host = ones.data();
   }
   RI_HIP(hipMemcpyAsync(P->mask_dev, mask_host, p.d, hipMemcpyHostToDevice, stream));
-  RI_TRY(ri::build_active(p, P->mask_dev, P->stats, stream));  // zeroes the active blocks' sums
-  RI_TRY(ri::fft_forward(p, P->xt, p.grid, stream));
+  // zeroes the active blocks' sums
+  RI_STAGE(P, RI_STAGE_ACTIVE, stream, ri::build_active(p, P->mask_dev, P->stats, stream));
+  RI_STAGE(P, RI_STAGE_FFT_ROWS, stream, ri::fft_forward_rows(p, P->xt, stream));
+  RI_STAGE(P, RI_STAGE_FFT_COLS, stream, ri::fft_forward_cols(p, p.grid, stream));
+  RI_TRY(ri::stage_begin(P, RI_STAGE_DEGRID, stream));
   for (int i = 0; i < p.d; ++i) {
     if (!mask_host[i]) continue;
     const int a = p.item_off_host[i], b = p.item_off_host[i + 1];
     RI_TRY(ri::degrid_residual(p, p.grid, P->y, P->v, P->e, P->stats, nullptr, nullptr, a, b - a, stream));
   }
+  RI_TRY(ri::stage_end(P, RI_STAGE_DEGRID, stream));
+  RI_TRY(ri::stage_begin(P, RI_STAGE_GRID, stream));
   for (int i = 0; i < p.d; ++i) {
     if (!mask_host[i]) continue;
     const int a = p.item_off_host[i], b = p.item_off_host[i + 1];
     RI_TRY(ri::grid_project(p, P->e, P->v, P->stats, P->eps, P->sum, nullptr, nullptr, a, b - a, stream));
   }
-  RI_TRY(ri::fft_adjoint(p, P->sum, P->g, stream));
-  RI_TRY(ri::export_stats(P, P->mask_dev, stats, stream));
+  RI_TRY(ri::stage_end(P, RI_STAGE_GRID, stream));
+  RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
+  RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows(p, P->g, stream));
+  RI_STAGE(P, RI_STAGE_STATS, stream, ri::export_stats(P, P->mask_dev, stats, stream));
   RI_TRY(ri::sparsity_branch(P, stream));
   RI_TRY(ri::primal_update(P, stream));
   P->iter += 1;
+  return RI_OK;
+}
+
+int ri_pd_timing(ri_pd P, int enable) {
+  if (!P) return fail(RI_EINVAL, "pd is NULL");
+  for (auto& r : P->recs) {
+    P->pool.push_back(r.a);
+    P->pool.push_back(r.b);
+  }
+  P->recs.clear();
+  P->timing = enable != 0;
+  return RI_OK;
+}
+
+int ri_pd_stage_times(ri_pd P, double* total_ms, int* launches, int n) {
+  if (!P || !total_ms || !launches || n < 1) return fail(RI_EINVAL, "bad argument");
+  for (int i = 0; i < n; ++i) {
+    total_ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  for (auto& r : P->recs) {
+    RI_HIP(hipEventSynchronize(r.b));
+    float ms = 0.f;
+    RI_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    if (r.stage < n) {
+      total_ms[r.stage] += ms;
+      launches[r.stage] += 1;
+    }
+    P->pool.push_back(r.a);
+    P->pool.push_back(r.b);
+  }
+  P->recs.clear();
   return RI_OK;
 }
 

@@ -59,6 +59,11 @@ struct Plan {
 int fft_forward(const Plan& p, const float* x, float2* grid, hipStream_t s);
 // x = Re S Z^dagger F^dagger grid (x: n*n real).
 int fft_adjoint(const Plan& p, const float2* grid, float* x, hipStream_t s);
+// The two passes of each, through the plan's n x K row buffer.
+int fft_forward_rows(const Plan& p, const float* x, hipStream_t s);
+int fft_forward_cols(const Plan& p, float2* grid, hipStream_t s);
+int fft_adjoint_cols(const Plan& p, const float2* grid, hipStream_t s);
+int fft_adjoint_rows(const Plan& p, float* x, hipStream_t s);
 
 // ---- launchers implemented in gridding.hip ----
 // Active work list of the blocks selected by mask (NULL = all) into p.active_list.

@@ -198,6 +198,18 @@ class PD:
     def refresh(self):
         L.check(L.load().ri_pd_refresh(self._h, _stream()))
 
+    def timing(self, enable=True):
+        """Record a HIP event pair around every stage of the following steps."""
+        L.check(L.load().ri_pd_timing(self._h, 1 if enable else 0))
+
+    def stage_times(self):
+        """{stage: (total ms, launches)} since timing was enabled; clears the records."""
+        n = len(L.STAGES)
+        tot = np.zeros(n)
+        cnt = np.zeros(n, dtype=np.int32)
+        L.check(L.load().ri_pd_stage_times(self._h, tot.ctypes.data, cnt.ctypes.data, n))
+        return {name: (float(tot[i]), int(cnt[i])) for i, name in enumerate(L.STAGES)}
+
     def _shape(self, which):
         n = self.plan.n
         return {L.RI_PD_X: ((n, n), torch.float32), L.RI_PD_XTILDE: ((n, n), torch.float32),
