@@ -71,7 +71,7 @@ int ri_hip_runtime_version(int* out);
 /* Tuning knobs of a plan.  Zero fields take the defaults. */
 typedef struct {
   int tile;           /* grid tile side in cells (16, 32 or 64; default 32)            */
-  int bin;            /* max visibilities per work item (default 1024)                 */
+  int bin;            /* max visibilities per work item (<= 1024; default 1024)        */
   int fft_panel;      /* columns per workgroup in the column FFT passes (default auto) */
   int persistent_wgs; /* workgroups of the persistent gather/scatter kernels (auto)    */
 } ri_tuning;

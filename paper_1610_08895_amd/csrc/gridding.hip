@@ -10,13 +10,22 @@
 //                    sum_i M_i^dagger v~_i.  Blocks outside A are not visited, so their v_i
 //                    and v~_i stay as they are.
 //
-// Visibilities are sorted by (block, tile, cell).  A work item covers up to `bin`
-// visibilities of one block in one T x T grid tile; its workgroup stages the tile plus
-// the kernel's reach (3 cells before, 4 after, per axis) in LDS, so every one of the 64
-// taps of a visibility is an LDS access.  Gridding accumulates into the LDS tile with
-// LDS float atomics and flushes the nonzero cells with global float atomics.  Kernels
-// are persistent: a fixed grid of workgroups walks the active item list, which lives in
-// device memory so a captured graph replays with whatever mask is current.
+// Visibilities are sorted by (block, tile, cell); a work item holds up to `bin`
+// visibilities of one block in one T x T grid tile.
+//
+// Degridding walks the active items with a persistent grid of workgroups; each stages
+// its tile plus the kernel's reach (3 cells before, 4 after, per axis) in LDS so all 64
+// taps of a visibility are LDS reads.  Block norms are accumulated per item in FP64 and
+// reduced per block by a second kernel in a fixed order (no atomics, deterministic).
+//
+// Gridding is owner-computes per tile: one workgroup accumulates every active item of a
+// tile (all blocks) into an LDS copy of the tile and its reach (exact integer LDS atomics
+// per item, see k_grid_tiles), then adds it to the grid with a plain read-modify-write.  Tiles are processed in four
+// launches by colour (ty mod 2, tx mod 2); two tiles of one colour are a full tile apart,
+// so their reaches never overlap and no global atomics are needed.  Inside an item,
+// consecutive lanes take visibilities a stride apart in sorted order, so lanes of one
+// LDS atomic instruction rarely hit the same cell.  Items whose values are all zero (a
+// block whose dual did not change) are skipped.
 #include "plan.hpp"
 
 namespace ri {
@@ -49,7 +58,7 @@ struct ItemSource {
   const int* count;  // device count of `list`
   int base, count_host;
   __device__ __forceinline__ int n() const { return list ? *count : count_host; }
-  __device__ __forceinline__ Item get(int a) const { return items[list ? list[a] : base + a]; }
+  __device__ __forceinline__ int index(int a) const { return list ? list[a] : base + a; }
 };
 
 enum { DG_APPLY = 0, DG_RESIDUAL = 1 };
@@ -58,13 +67,14 @@ template <int T, int MODE>
 __global__ __launch_bounds__(GT) void k_degrid(ItemSource src, const uint2* __restrict__ coord,
                                                const float2* __restrict__ grid, int K, int tpa, KBPoly P,
                                                float2* __restrict__ out, const float2* __restrict__ y,
-                                               const float2* __restrict__ v, double* __restrict__ stats) {
+                                               const float2* __restrict__ v, double* __restrict__ part) {
   constexpr int TW = T + 8;
   __shared__ float2 tile[TW * TW];
   __shared__ double red[2][GT / 64];
   const int nitems = src.n();
   for (int a = blockIdx.x; a < nitems; a += gridDim.x) {
-    const Item it = src.get(a);
+    const int iidx = src.index(a);
+    const Item it = src.items[iidx];
     const int ty = it.y / tpa, tx = it.y - (it.y / tpa) * tpa;
     const int gy0 = ty * T - (KB_J / 2 - 1), gx0 = tx * T - (KB_J / 2 - 1);
     for (int idx = threadIdx.x; idx < TW * TW; idx += GT) {
@@ -123,75 +133,158 @@ __global__ __launch_bounds__(GT) void k_degrid(ItemSource src, const uint2* __re
           a0 += red[0][k];
           a1 += red[1][k];
         }
-        unsafeAtomicAdd(&stats[2 * it.x], a0);
-        unsafeAtomicAdd(&stats[2 * it.x + 1], a1);
+        part[2 * iidx] = a0;
+        part[2 * iidx + 1] = a1;
       }
     }
     __syncthreads();
   }
 }
 
+// stats[2i], stats[2i+1] = sums of the per-item partials of block i, for active blocks.
+__global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ mask, const int* __restrict__ item_off,
+                                                    const double* __restrict__ part, double* __restrict__ stats) {
+  __shared__ double red[2][GT / 64];
+  const int i = blockIdx.x;
+  if (mask != nullptr && mask[i] == 0) return;
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = item_off[i] + threadIdx.x; k < item_off[i + 1]; k += GT) {
+    a0 += part[2 * k];
+    a1 += part[2 * k + 1];
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x / 64] = a0;
+    red[1][threadIdx.x / 64] = a1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int k = 0; k < GT / 64; ++k) {
+      s0 += red[0][k];
+      s1 += red[1][k];
+    }
+    stats[2 * i] = s0;
+    stats[2 * i + 1] = s1;
+  }
+}
+
 enum { GR_APPLY = 0, GR_PROJECT = 1 };
 
+// A gridding unit: one tile and the range [b, e) of idx[] listing the items that fall in
+// it (x = tile, y = b, z = e).
+//
+// Per item the contributions are accumulated exactly in LDS with 32-bit integer atomics
+// (on this hardware LDS integer atomics are an order of magnitude faster than LDS float
+// atomics): every value is scaled by a power of two 2^E chosen from the item's sum of
+// |Re| + |Im|, which bounds any cell's sum, so |sum| * 2^E < 2^30 and nothing overflows.
+// Rounding is at most 2^-E-1 per contribution.  The integer tile is then folded into a
+// float tile, which after all items is added to the grid.
 template <int T, int MODE>
-__global__ __launch_bounds__(GT) void k_grid(ItemSource src, const uint2* __restrict__ coord,
-                                             float2* __restrict__ grid, int K, int tpa, KBPoly P,
-                                             const float2* __restrict__ y, const float2* __restrict__ e,
-                                             float2* __restrict__ v, const double* __restrict__ stats,
-                                             const double* __restrict__ eps) {
+__global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ units, int nunits,
+                                                   const int* __restrict__ idx_list, const Item* __restrict__ items,
+                                                   const uint8_t* __restrict__ mask, const uint2* __restrict__ coord,
+                                                   float2* __restrict__ grid, int K, int tpa, KBPoly P,
+                                                   const float2* __restrict__ y, const float2* __restrict__ e,
+                                                   float2* __restrict__ v, const double* __restrict__ stats,
+                                                   const double* __restrict__ eps) {
   constexpr int TW = T + 8;
-  __shared__ float acc[2][TW * TW];
-  const int nitems = src.n();
-  for (int a = blockIdx.x; a < nitems; a += gridDim.x) {
-    const Item it = src.get(a);
-    const int ty = it.y / tpa, tx = it.y - (it.y / tpa) * tpa;
-    for (int idx = threadIdx.x; idx < TW * TW; idx += GT) {
-      acc[0][idx] = 0.f;
-      acc[1][idx] = 0.f;
+  __shared__ float accf[2][TW * TW];
+  __shared__ int acci[2][TW * TW];
+  __shared__ float2 vals[MAX_BIN];
+  __shared__ float red[GT / 64];
+  const int lane = threadIdx.x & 63;
+  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const int4 un = units[u];
+    const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
+    for (int k = threadIdx.x; k < TW * TW; k += GT) {
+      accf[0][k] = 0.f;
+      accf[1][k] = 0.f;
     }
-    float shrink = 0.f;
-    if (MODE == GR_PROJECT) {
-      const double nr2 = stats[2 * it.x], ep = eps[it.x];
-      shrink = nr2 > ep * ep ? float(1.0 - ep / sqrt(nr2)) : 0.f;
-    }
-    __syncthreads();
-    const int end = it.z + it.w;
-    for (int m = it.z + threadIdx.x; m < end; m += GT) {
-      float2 val;
-      if (MODE == GR_APPLY) {
-        val = y[m];
-      } else {
-        const float2 vo = v[m], ee = e[m];
-        const float2 vn = make_float2((vo.x + ee.x) * shrink, (vo.y + ee.y) * shrink);
-        v[m] = vn;
-        val = make_float2(vn.x - vo.x, vn.y - vo.y);
+    for (int q = un.y; q < un.z; ++q) {
+      const Item it = items[idx_list[q]];
+      if (mask != nullptr && mask[it.x] == 0) continue;
+      float shrink = 0.f;
+      if (MODE == GR_PROJECT) {
+        const double nr2 = stats[2 * it.x], ep = eps[it.x];
+        shrink = nr2 > ep * ep ? float(1.0 - ep / sqrt(nr2)) : 0.f;
       }
-      const uint2 c = coord[m];
-      float wx[KB_J], wy[KB_J];
-      int cx, cy;
-      kb_weights(c.x, P, wx, cx);
-      kb_weights(c.y, P, wy, cy);
-      const int b0 = (cy - ty * T) * TW + (cx - tx * T);
+      // values (and the dual update of step 8), and the bound sum |Re| + |Im|
+      float babs = 0.f;
+      for (int s = threadIdx.x; s < it.w; s += GT) {
+        const int m = it.z + s;
+        float2 val;
+        if (MODE == GR_APPLY) {
+          val = y[m];
+        } else {
+          const float2 vo = v[m], ee = e[m];
+          const float2 vn = make_float2((vo.x + ee.x) * shrink, (vo.y + ee.y) * shrink);
+          v[m] = vn;
+          val = make_float2(vn.x - vo.x, vn.y - vo.y);
+        }
+        vals[s] = val;
+        babs += fabsf(val.x) + fabsf(val.y);
+      }
+      for (int off = 32; off > 0; off >>= 1) babs += __shfl_xor(babs, off, 64);
+      if (lane == 0) red[threadIdx.x / 64] = babs;
+      for (int k = threadIdx.x; k < TW * TW; k += GT) {
+        acci[0][k] = 0;
+        acci[1][k] = 0;
+      }
+      __syncthreads();
+      float bound = 0.f;
 #pragma unroll
-      for (int ra = 0; ra < KB_J; ++ra) {
-        const float tr = wy[ra] * val.x, ti = wy[ra] * val.y;
+      for (int k = 0; k < GT / 64; ++k) bound += red[k];
+      if (bound == 0.f) {  // the item changes nothing
+        __syncthreads();
+        continue;
+      }
+      // 2^E with bound * 2^E <= 2^30 (bound * 1.0001 guards the bound's own rounding)
+      int ex;
+      frexpf(bound * 1.0001f, &ex);
+      const float scale = ldexpf(1.f, 30 - ex), inv = ldexpf(1.f, ex - 30);
+      const int S = (it.w + 63) >> 6;  // visibilities per lane slot
+      for (int j = threadIdx.x; j < 64 * S; j += GT) {
+        const int s = lane * S + (j >> 6);
+        if (s >= it.w) continue;
+        const uint2 c = coord[it.z + s];
+        const float2 val = vals[s];
+        float wx[KB_J], wy[KB_J];
+        int cx, cy;
+        kb_weights(c.x, P, wx, cx);
+        kb_weights(c.y, P, wy, cy);
+        const int b0 = (cy - ty * T) * TW + (cx - tx * T);
 #pragma unroll
-        for (int b = 0; b < KB_J; ++b) {
-          atomicAdd(&acc[0][b0 + ra * TW + b], wx[b] * tr);
-          atomicAdd(&acc[1][b0 + ra * TW + b], wx[b] * ti);
+        for (int ra = 0; ra < KB_J; ++ra) {
+          const float tr = wy[ra] * val.x * scale, ti = wy[ra] * val.y * scale;
+#pragma unroll
+          for (int b = 0; b < KB_J; ++b) {
+            atomicAdd(&acci[0][b0 + ra * TW + b], __float2int_rn(wx[b] * tr));
+            atomicAdd(&acci[1][b0 + ra * TW + b], __float2int_rn(wx[b] * ti));
+          }
         }
       }
+      __syncthreads();
+      for (int k = threadIdx.x; k < TW * TW; k += GT) {
+        const int ir = acci[0][k], ii = acci[1][k];
+        if (ir | ii) {
+          accf[0][k] += float(ir) * inv;
+          accf[1][k] += float(ii) * inv;
+        }
+      }
+      __syncthreads();
     }
     __syncthreads();
     const int gy0 = ty * T - (KB_J / 2 - 1), gx0 = tx * T - (KB_J / 2 - 1);
-    for (int idx = threadIdx.x; idx < TW * TW; idx += GT) {
-      const float re = acc[0][idx], im = acc[1][idx];
+    for (int k = threadIdx.x; k < TW * TW; k += GT) {
+      const float re = accf[0][k], im = accf[1][k];
       if (re != 0.f || im != 0.f) {
-        const int ly = idx / TW, lx = idx - ly * TW;
+        const int ly = k / TW, lx = k - ly * TW;
         const int gy = (gy0 + ly) & (K - 1), gx = (gx0 + lx) & (K - 1);
-        float* g = reinterpret_cast<float*>(&grid[size_t(gy) * K + gx]);
-        unsafeAtomicAdd(g, re);
-        unsafeAtomicAdd(g + 1, im);
+        float2* g = &grid[size_t(gy) * K + gx];
+        const float2 old = *g;
+        *g = make_float2(old.x + re, old.y + im);
       }
     }
     __syncthreads();
@@ -199,28 +292,25 @@ __global__ __launch_bounds__(GT) void k_grid(ItemSource src, const uint2* __rest
 }
 
 __global__ void k_build_active(const uint8_t* __restrict__ mask, int d, const int* __restrict__ item_off,
-                               int* __restrict__ list, int* __restrict__ count, double* __restrict__ stats) {
+                               int* __restrict__ list, int* __restrict__ count) {
   int pos = 0;
   for (int i = 0; i < d; ++i) {
     if (mask == nullptr || mask[i] != 0) {
       const int a = item_off[i], b = item_off[i + 1];
       for (int t = threadIdx.x; t < b - a; t += blockDim.x) list[pos + t] = a + t;
       pos += b - a;
-      if (stats != nullptr && threadIdx.x == 0) {
-        stats[2 * i] = 0.0;
-        stats[2 * i + 1] = 0.0;
-      }
     }
   }
   if (threadIdx.x == 0) *count = pos;
 }
 
 __global__ __launch_bounds__(GT) void k_block_sumsq(ItemSource src, const float2* __restrict__ y,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ part) {
   __shared__ double red[GT / 64];
   const int nitems = src.n();
   for (int a = blockIdx.x; a < nitems; a += gridDim.x) {
-    const Item it = src.get(a);
+    const int iidx = src.index(a);
+    const Item it = src.items[iidx];
     double acc = 0.0;
     for (int m = it.z + threadIdx.x; m < it.z + it.w; m += GT) {
       const float2 v = y[m];
@@ -232,15 +322,48 @@ __global__ __launch_bounds__(GT) void k_block_sumsq(ItemSource src, const float2
     if (threadIdx.x == 0) {
       double t = 0.0;
       for (int k = 0; k < GT / 64; ++k) t += red[k];
-      unsafeAtomicAdd(&out[it.x], t);
+      part[2 * iidx] = t;
+      part[2 * iidx + 1] = 0.0;
     }
     __syncthreads();
   }
 }
 
-int wgs_for(const Plan& p, int items) {
+__global__ void k_take_even(const double* __restrict__ in, double* __restrict__ out, int d) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d; i += gridDim.x * blockDim.x) out[i] = in[2 * i];
+}
+
+int wgs_for(const Plan& p, int units) {
   int g = p.persistent_wgs > 0 ? p.persistent_wgs : device_cus() * 8;
-  return items < g ? (items > 0 ? items : 1) : g;
+  return units < g ? (units > 0 ? units : 1) : g;
+}
+
+template <int T, int MODE>
+int launch_grid(const Plan& p, const int4* units, int nunits, const int* idx, const uint8_t* mask, float2* grid,
+                const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
+                hipStream_t s) {
+  if (nunits <= 0) return RI_OK;
+  hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GT), 0, s, units, nunits, idx,
+                     p.items, mask, p.coord, grid, p.K, p.tpa, p.poly, y, e, v, stats, eps);
+  RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+template <int MODE>
+int grid_phases(const Plan& p, const int4* units, const int* off, const int* idx, const uint8_t* mask,
+                float2* grid, const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
+                hipStream_t s) {
+  for (int c = 0; c < 4; ++c) {
+    const int4* u = units + off[c];
+    const int n = off[c + 1] - off[c];
+    switch (p.tile) {
+      case 16: RI_TRY((launch_grid<16, MODE>(p, u, n, idx, mask, grid, y, e, v, stats, eps, s))); break;
+      case 32: RI_TRY((launch_grid<32, MODE>(p, u, n, idx, mask, grid, y, e, v, stats, eps, s))); break;
+      case 64: RI_TRY((launch_grid<64, MODE>(p, u, n, idx, mask, grid, y, e, v, stats, eps, s))); break;
+      default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
+    }
+  }
+  return RI_OK;
 }
 
 #define RI_TILE_DISPATCH(KERNEL, ...)                                                          \
@@ -253,17 +376,27 @@ int wgs_for(const Plan& p, int items) {
 
 }  // namespace
 
-int build_active(const Plan& p, const uint8_t* mask, double* stats_zero, hipStream_t s) {
+int build_active(const Plan& p, const uint8_t* mask, hipStream_t s) {
   hipLaunchKernelGGL(k_build_active, dim3(1), dim3(256), 0, s, mask, p.d, p.item_off, p.active_list,
-                     p.active_count, stats_zero);
+                     p.active_count);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
 
+int block_stats(const Plan& p, const uint8_t* mask, double* stats, hipStream_t s);
+
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s) {
   ItemSource src{p.items, nullptr, nullptr, 0, p.n_items};
-  RI_TRY(zero_f32(reinterpret_cast<float*>(out), 2 * size_t(p.d), s));
-  hipLaunchKernelGGL(k_block_sumsq, dim3(wgs_for(p, p.n_items)), dim3(GT), 0, s, src, y, out);
+  hipLaunchKernelGGL(k_block_sumsq, dim3(wgs_for(p, p.n_items)), dim3(GT), 0, s, src, y, p.item_part);
+  RI_LAUNCH_CHECK();
+  RI_TRY(block_stats(p, nullptr, p.block_tmp, s));
+  hipLaunchKernelGGL(k_take_even, dim3((p.d + 255) / 256), dim3(256), 0, s, p.block_tmp, out, p.d);
+  RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+int block_stats(const Plan& p, const uint8_t* mask, double* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_stats, dim3(p.d), dim3(GT), 0, s, mask, p.item_off, p.item_part, stats);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
@@ -279,49 +412,36 @@ int degrid_apply(const Plan& p, const float2* grid, float2* y, hipStream_t s) {
 }
 
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
-                    double* stats, const int* list, const int* count, int base, int count_host,
-                    hipStream_t s) {
+                    const int* list, const int* count, int base, int count_host, hipStream_t s) {
   ItemSource src{p.items, list, count, base, count_host};
   const dim3 grid_dim(wgs_for(p, list ? p.n_items : count_host));
-#define ARGS src, p.coord, grid, p.K, p.tpa, p.poly, e, y, v, stats
+#define ARGS src, p.coord, grid, p.K, p.tpa, p.poly, e, y, v, p.item_part
   RI_TILE_DISPATCH(k_degrid, DG_RESIDUAL)
 #undef ARGS
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
 
-int grid_apply(const Plan& p, const float2* y, float2* grid, hipStream_t s) {
-  ItemSource src{p.items, p.active_list, p.active_count, 0, 0};
-  const dim3 grid_dim(wgs_for(p, p.n_items));
-#define ARGS src, p.coord, grid, p.K, p.tpa, p.poly, y, (const float2*)nullptr, (float2*)nullptr, \
-             (const double*)nullptr, (const double*)nullptr
-  RI_TILE_DISPATCH(k_grid, GR_APPLY)
-#undef ARGS
-  RI_LAUNCH_CHECK();
-  return RI_OK;
+int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s) {
+  return grid_phases<GR_APPLY>(p, p.units, p.phase_off_host, p.tile_items, mask, grid, y, nullptr, nullptr,
+                               nullptr, nullptr, s);
 }
 
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s) {
-  ItemSource src{p.items, nullptr, nullptr, 0, p.n_items};
-  const dim3 grid_dim(wgs_for(p, p.n_items));
-#define ARGS src, p.coord, grid, p.K, p.tpa, p.poly, v, (const float2*)nullptr, (float2*)nullptr, \
-             (const double*)nullptr, (const double*)nullptr
-  RI_TILE_DISPATCH(k_grid, GR_APPLY)
-#undef ARGS
-  RI_LAUNCH_CHECK();
-  return RI_OK;
+  return grid_phases<GR_APPLY>(p, p.units, p.phase_off_host, p.tile_items, nullptr, grid, v, nullptr, nullptr,
+                               nullptr, nullptr, s);
 }
 
 int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
-                 float2* grid, const int* list, const int* count, int base, int count_host,
-                 hipStream_t s) {
-  ItemSource src{p.items, list, count, base, count_host};
-  const dim3 grid_dim(wgs_for(p, list ? p.n_items : count_host));
-#define ARGS src, p.coord, grid, p.K, p.tpa, p.poly, (const float2*)nullptr, e, v, stats, eps
-  RI_TILE_DISPATCH(k_grid, GR_PROJECT)
-#undef ARGS
-  RI_LAUNCH_CHECK();
-  return RI_OK;
+                 const uint8_t* mask, float2* grid, hipStream_t s) {
+  return grid_phases<GR_PROJECT>(p, p.units, p.phase_off_host, p.tile_items, mask, grid, nullptr, e, v, stats,
+                                 eps, s);
+}
+
+int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const double* stats,
+                       const double* eps, float2* grid, hipStream_t s) {
+  return grid_phases<GR_PROJECT>(p, p.bunits, &p.bunit_off_host[4 * block], p.iota, nullptr, grid, nullptr, e,
+                                 v, stats, eps, s);
 }
 
 }  // namespace ri

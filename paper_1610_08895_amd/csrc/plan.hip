@@ -60,6 +60,12 @@ void destroy_plan(Plan& p) {
   dev_free(p.grid);
   dev_free(p.rowbuf);
   dev_free(p.active_list);
+  dev_free(p.tile_items);
+  dev_free(p.iota);
+  dev_free(p.units);
+  dev_free(p.bunits);
+  dev_free(p.item_part);
+  dev_free(p.block_tmp);
   dev_free(p.active_count);
   dev_free(p.norm_tmp);
   dev_free(p.dsum);
@@ -86,8 +92,10 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   p.beta = beta > 0 ? beta : 2.34 * J;
   p.tile = tune && tune->tile ? tune->tile : 32;
   if (p.tile != 16 && p.tile != 32 && p.tile != 64) return fail(RI_EINVAL, "tile must be 16, 32 or 64");
-  if (p.tile > p.K) p.tile = 16;
-  p.bin = tune && tune->bin > 0 ? tune->bin : 1024;
+  // gridding phases need two tiles per axis at least (same-colour tiles must not touch)
+  while (p.tile > 16 && p.tile > p.K / 2) p.tile /= 2;
+  p.bin = tune && tune->bin > 0 ? tune->bin : MAX_BIN;
+  if (p.bin > MAX_BIN) return fail(RI_EINVAL, "bin=%d exceeds %d", p.bin, MAX_BIN);
   p.fft_panel = tune ? tune->fft_panel : 0;
   p.persistent_wgs = tune ? tune->persistent_wgs : 0;
   p.tpa = p.K / p.tile;
@@ -156,6 +164,42 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   p.item_off_host[d] = int(items.size());
   p.n_items = int(items.size());
 
+  // items grouped by tile, and tiles grouped into the four gridding colours
+  p.n_tiles = tpa * tpa;
+  std::vector<int> tile_cnt(p.n_tiles + 1, 0), tile_vis(p.n_tiles, 0);
+  for (const Item& it : items) {
+    tile_cnt[it.y + 1] += 1;
+    tile_vis[it.y] += it.w;
+  }
+  for (int t = 0; t < p.n_tiles; ++t) tile_cnt[t + 1] += tile_cnt[t];
+  std::vector<int> tile_items(items.size()), fill(tile_cnt.begin(), tile_cnt.end() - 1);
+  for (int k = 0; k < int(items.size()); ++k) tile_items[fill[items[k].y]++] = k;
+  auto colour = [&](int t) { return ((t / tpa) & 1) * 2 + ((t % tpa) & 1); };
+  std::vector<int4> units, bunits;
+  for (int c = 0; c < 4; ++c) {
+    p.phase_off_host[c] = int(units.size());
+    std::vector<int> ts;
+    for (int t = 0; t < p.n_tiles; ++t)
+      if (tile_vis[t] > 0 && colour(t) == c) ts.push_back(t);
+    std::stable_sort(ts.begin(), ts.end(), [&](int a, int b) { return tile_vis[a] > tile_vis[b]; });
+    for (int t : ts) units.push_back(make_int4(t, tile_cnt[t], tile_cnt[t + 1], 0));
+  }
+  p.phase_off_host[4] = int(units.size());
+  p.bunit_off_host.assign(4 * size_t(d) + 1, 0);
+  for (int i = 0; i < d; ++i)
+    for (int c = 0; c < 4; ++c) {
+      p.bunit_off_host[4 * i + c] = int(bunits.size());
+      for (int k = p.item_off_host[i]; k < p.item_off_host[i + 1];) {
+        int e = k;
+        while (e < p.item_off_host[i + 1] && items[e].y == items[k].y) ++e;
+        if (colour(items[k].y) == c) bunits.push_back(make_int4(items[k].y, k, e, 0));
+        k = e;
+      }
+    }
+  p.bunit_off_host[4 * d] = int(bunits.size());
+  std::vector<int> iota(items.size());
+  for (size_t k = 0; k < iota.size(); ++k) iota[k] = int(k);
+
   std::vector<float2> tw(K);
   for (int k = 0; k < K; ++k) {
     const double a = -2.0 * M_PI * k / K;
@@ -173,6 +217,12 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.grid, size_t(K) * K));
   RI_TRY(dev_alloc(&p.rowbuf, size_t(n) * K));
   RI_TRY(dev_alloc(&p.active_list, items.size()));
+  RI_TRY(dev_alloc(&p.tile_items, items.size()));
+  RI_TRY(dev_alloc(&p.iota, items.size()));
+  RI_TRY(dev_alloc(&p.units, units.size()));
+  RI_TRY(dev_alloc(&p.bunits, bunits.size()));
+  RI_TRY(dev_alloc(&p.item_part, 2 * items.size()));
+  RI_TRY(dev_alloc(&p.block_tmp, 2 * size_t(d)));
   RI_TRY(dev_alloc(&p.active_count, 1));
   RI_TRY(dev_alloc(&p.norm_tmp, size_t(n) * n));
   RI_TRY(dev_alloc(&p.dsum, SUMSQ_SCRATCH));
@@ -181,6 +231,10 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_HIP(hipMemcpyAsync(p.items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.item_off, p.item_off_host.data(), (d + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.twiddle, tw.data(), K * sizeof(float2), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.tile_items, tile_items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.iota, iota.data(), iota.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.bunits, bunits.data(), bunits.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.scale, sc.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
   RI_HIP(hipStreamSynchronize(s));
   return RI_OK;
@@ -189,15 +243,14 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
 }  // namespace
 
 int phi_apply(const Plan& p, const float* x, float* y, const uint8_t* mask, hipStream_t s) {
-  RI_TRY(build_active(p, mask, nullptr, s));
+  RI_TRY(build_active(p, mask, s));
   RI_TRY(fft_forward(p, x, p.grid, s));
   return degrid_apply(p, p.grid, reinterpret_cast<float2*>(y), s);
 }
 
 int phi_adj_apply(const Plan& p, const float* y, float* x, const uint8_t* mask, hipStream_t s) {
-  RI_TRY(build_active(p, mask, nullptr, s));
   RI_TRY(zero_c64(p.grid, size_t(p.K) * p.K, s));
-  RI_TRY(grid_apply(p, reinterpret_cast<const float2*>(y), p.grid, s));
+  RI_TRY(grid_apply(p, reinterpret_cast<const float2*>(y), mask, p.grid, s));
   return fft_adjoint(p, p.grid, x, s);
 }
 

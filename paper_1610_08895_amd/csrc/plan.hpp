@@ -23,6 +23,7 @@ constexpr unsigned FRAC_MASK = (1u << FRAC_BITS) - 1u;
 // A work item: up to `bin` visibilities of one block that fall in one grid tile.
 // x = block, y = tile (ty * tiles_per_axis + tx), z = first plan position, w = count.
 using Item = int4;
+constexpr int MAX_BIN = 1024;  // largest `bin` (the gridding kernel stages an item's values in LDS)
 
 struct Plan {
   int n = 0, K = 0, J = KB_J, d = 0;
@@ -36,6 +37,11 @@ struct Plan {
   double poly_err = 0.0;
 
   std::vector<int> item_off_host;  // d + 1
+  int n_tiles = 0;                  // tpa * tpa
+  // gridding units {tile, first, end} over an item index list, in four colour phases
+  // (colour (ty & 1) * 2 + (tx & 1)): all blocks together, and block by block
+  int phase_off_host[5] = {0};
+  std::vector<int> bunit_off_host;  // 4 d + 1
   std::vector<int64_t> order_host;  // plan position -> user index
   std::vector<int64_t> block_off_host;
 
@@ -49,6 +55,12 @@ struct Plan {
   float2* grid = nullptr;     // K * K work grid
   float2* rowbuf = nullptr;   // n * K half-transformed rows
   int* active_list = nullptr; // n_items
+  int* tile_items = nullptr;    // n_items, grouped by tile (all blocks)
+  int* iota = nullptr;          // n_items: 0, 1, 2, ...
+  int4* units = nullptr;        // tiles with items, by colour, densest first; ranges into tile_items
+  int4* bunits = nullptr;       // per block and colour; ranges into iota
+  double* item_part = nullptr;  // 2 * n_items per-item partial sums of the block norms
+  double* block_tmp = nullptr;  // 2 * d
   int* active_count = nullptr;
   float* norm_tmp = nullptr;  // n * n scratch for power iterations
   double* dsum = nullptr;     // FP64 reduction scratch
@@ -67,21 +79,25 @@ int fft_adjoint_rows(const Plan& p, float* x, hipStream_t s);
 
 // ---- launchers implemented in gridding.hip ----
 // Active work list of the blocks selected by mask (NULL = all) into p.active_list.
-int build_active(const Plan& p, const uint8_t* mask, double* stats_zero, hipStream_t s);
+int build_active(const Plan& p, const uint8_t* mask, hipStream_t s);
+// stats[2i], stats[2i+1] = per-block sums of the degridding partials, active blocks only.
+int block_stats(const Plan& p, const uint8_t* mask, double* stats, hipStream_t s);
 // out[i] = ||y_i||^2 (FP64) for every block.
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s);
 // y = G b for the active items (operator form).
 int degrid_apply(const Plan& p, const float2* grid, float2* y, hipStream_t s);
-// grid += G^dagger y for the active items (operator form; grid zeroed by the caller).
-int grid_apply(const Plan& p, const float2* y, float2* grid, hipStream_t s);
-// PD residual pass: e = G b - y, r = v + e; stats[2i] += ||r||^2, stats[2i+1] += ||e||^2.
+// grid += G^dagger y for the active blocks (operator form; grid zeroed by the caller).
+int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s);
+// PD residual pass: e = G b - y, r = v + e; stats[2i] = ||r_i||^2, stats[2i+1] = ||e_i||^2 for the
+// blocks whose items are processed (per-item partial sums, then a per-block reduction).
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
-                    double* stats, const int* list, const int* count, int base, int count_host,
-                    hipStream_t s);
-// PD projection pass: v_new = (v + e) max(0, 1 - eps/||r||); grid += G^dagger (v_new - v); v = v_new.
+                    const int* list, const int* count, int base, int count_host, hipStream_t s);
+// PD projection pass: v_new = (v + e) max(0, 1 - eps/||r||); grid += G^dagger (v_new - v); v = v_new,
+// for the active blocks (all tiles, four colour launches) or for one block.
 int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
-                 float2* grid, const int* list, const int* count, int base, int count_host,
-                 hipStream_t s);
+                 const uint8_t* mask, float2* grid, hipStream_t s);
+int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const double* stats,
+                       const double* eps, float2* grid, hipStream_t s);
 // grid += G^dagger v over all items (used to rebuild the running sum from scratch).
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s);
 
