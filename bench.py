@@ -74,6 +74,7 @@ def main():
     ap.add_argument("--op-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="grid tile side (0: library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of "
@@ -94,7 +95,7 @@ def main():
     t0 = time.time()
     inp = synth.make_inputs(w)
     log(f"inputs {time.time() - t0:.1f}s")
-    plan = R.Plan(w.n, inp.uv, inp.block_off)
+    plan = R.Plan(w.n, inp.uv, inp.block_off, tile=args.tile)
     order = plan.order()
     log(f"plan {time.time() - t0:.1f}s items={plan.n_items}")
     x_true = torch.tensor(inp.x_true, dtype=torch.float32, device="cuda")
@@ -211,7 +212,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": w.n, "M": w.M, "d": plan.d, "p": 1.0,
+        "config": {"workload": WORKLOAD, "n": w.n, "M": w.M, "d": plan.d, "p": 1.0, "tile": plan.tile,
                    "form": "batched persistent kernels" + (" + HIP graph" if use_graph else ""),
                    "kernel": "Kaiser-Bessel 8x8, 2x oversampling", "sara": "Dirac + db1..db8, 4 levels"},
         "phi_gvis_s": round(w.M / phi_ms / 1e6, 2),

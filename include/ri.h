@@ -128,8 +128,8 @@ int ri_phi_norm(ri_plan plan, float* x0, int max_it, double rtol, double* norm_h
  * g[j] = (-1)^j h[2N-1-j], the minimum-phase Daubechies lowpass h with sum h = sqrt 2.
  * ------------------------------------------------------------------------------------ */
 
-/* bases: bit 0 = Dirac, bit k (1..8) = db_k; 0 selects all nine.  n divisible by
- * 2^levels, 1 <= levels <= 6.  Errors: RI_EINVAL, RI_ENOMEM, RI_EHIP. */
+/* bases: bit 0 = Dirac, bit k (1..8) = db_k; 0 selects all nine.  n a power of two with
+ * 2^levels <= n <= 4096, 1 <= levels <= 6.  Errors: RI_EINVAL, RI_ENOMEM, RI_EHIP. */
 int ri_sara_create(ri_sara* out, int n, int levels, uint32_t bases, hipStream_t stream);
 void ri_sara_destroy(ri_sara sara);
 /* Number of bases b. */

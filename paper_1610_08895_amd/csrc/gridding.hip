@@ -20,9 +20,11 @@
 //
 // Gridding is owner-computes per tile: one workgroup accumulates every active item of a
 // tile (all blocks) into an LDS copy of the tile and its reach (exact integer LDS atomics
-// per item, see k_grid_tiles), then adds it to the grid with a plain read-modify-write.  Tiles are processed in four
-// launches by colour (ty mod 2, tx mod 2); two tiles of one colour are a full tile apart,
-// so their reaches never overlap and no global atomics are needed.  Inside an item,
+// per item, see k_grid_tiles), adds the tile interior to the grid with a plain
+// read-modify-write (no other workgroup writes it) and stores the reach outside the
+// interior in a per-tile halo patch; a second kernel adds the neighbours' patches into
+// each tile's border cells.  No global atomics are needed, and one launch covers all tiles
+// (densest first).  Inside an item,
 // consecutive lanes take visibilities a stride apart in sorted order, so lanes of one
 // LDS atomic instruction rarely hit the same cell.  Items whose values are all zero (a
 // block whose dual did not change) are skipped.
@@ -175,33 +177,34 @@ enum { GR_APPLY = 0, GR_PROJECT = 1 };
 // A gridding unit: one tile and the range [b, e) of idx[] listing the items that fall in
 // it (x = tile, y = b, z = e).
 //
-// Per item the contributions are accumulated exactly in LDS with 32-bit integer atomics
-// (on this hardware LDS integer atomics are an order of magnitude faster than LDS float
-// atomics): every value is scaled by a power of two 2^E chosen from the item's sum of
-// |Re| + |Im|, which bounds any cell's sum, so |sum| * 2^E < 2^30 and nothing overflows.
-// Rounding is at most 2^-E-1 per contribution.  The integer tile is then folded into a
-// float tile, which after all items is added to the grid.
+// Per item the contributions are accumulated exactly in LDS with 64-bit integer atomics
+// (LDS integer atomics are an order of magnitude faster than LDS float atomics on this
+// hardware), Re in the low and Im in the high 32 bits of one word: every value is scaled
+// by a power of two 2^E chosen from the item's sum of |Re| + |Im|, which bounds any cell's
+// sum, so each field stays below 2^30 in magnitude; the low field's sign borrows from the
+// high field exactly, and decoding subtracts the sign-extended low field.  Rounding is at
+// most 2^-E-1 per contribution.  The integer tile is folded into a float tile after each
+// item.  At the end the tile interior (owned by this workgroup alone) is added to the grid
+// and the reach outside it is stored in the tile's halo patch for k_grid_halo.
 template <int T, int MODE>
 __global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ units, int nunits,
                                                    const int* __restrict__ idx_list, const Item* __restrict__ items,
                                                    const uint8_t* __restrict__ mask, const uint2* __restrict__ coord,
-                                                   float2* __restrict__ grid, int K, int tpa, KBPoly P,
-                                                   const float2* __restrict__ y, const float2* __restrict__ e,
-                                                   float2* __restrict__ v, const double* __restrict__ stats,
-                                                   const double* __restrict__ eps) {
+                                                   float2* __restrict__ grid, float2* __restrict__ halo, int K,
+                                                   int tpa, KBPoly P, const float2* __restrict__ y,
+                                                   const float2* __restrict__ e, float2* __restrict__ v,
+                                                   const double* __restrict__ stats, const double* __restrict__ eps) {
   constexpr int TW = T + 8;
-  __shared__ float accf[2][TW * TW];
-  __shared__ int acci[2][TW * TW];
+  constexpr int R0 = KB_J / 2 - 1;  // reach before the tile
+  __shared__ float2 accf[TW * TW];
+  __shared__ unsigned long long acci[TW * TW];
   __shared__ float2 vals[MAX_BIN];
   __shared__ float red[GT / 64];
   const int lane = threadIdx.x & 63;
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int4 un = units[u];
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
-    for (int k = threadIdx.x; k < TW * TW; k += GT) {
-      accf[0][k] = 0.f;
-      accf[1][k] = 0.f;
-    }
+    for (int k = threadIdx.x; k < TW * TW; k += GT) accf[k] = make_float2(0.f, 0.f);
     for (int q = un.y; q < un.z; ++q) {
       const Item it = items[idx_list[q]];
       if (mask != nullptr && mask[it.x] == 0) continue;
@@ -228,10 +231,7 @@ __global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ unit
       }
       for (int off = 32; off > 0; off >>= 1) babs += __shfl_xor(babs, off, 64);
       if (lane == 0) red[threadIdx.x / 64] = babs;
-      for (int k = threadIdx.x; k < TW * TW; k += GT) {
-        acci[0][k] = 0;
-        acci[1][k] = 0;
-      }
+      for (int k = threadIdx.x; k < TW * TW; k += GT) acci[k] = 0ull;
       __syncthreads();
       float bound = 0.f;
 #pragma unroll
@@ -260,48 +260,110 @@ __global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ unit
           const float tr = wy[ra] * val.x * scale, ti = wy[ra] * val.y * scale;
 #pragma unroll
           for (int b = 0; b < KB_J; ++b) {
-            atomicAdd(&acci[0][b0 + ra * TW + b], __float2int_rn(wx[b] * tr));
-            atomicAdd(&acci[1][b0 + ra * TW + b], __float2int_rn(wx[b] * ti));
+            const int ir = __float2int_rn(wx[b] * tr), ii = __float2int_rn(wx[b] * ti);
+            const unsigned long long w64 =
+                (static_cast<unsigned long long>(static_cast<unsigned>(ii + (ir >> 31))) << 32) |
+                static_cast<unsigned>(ir);
+            atomicAdd(&acci[b0 + ra * TW + b], w64);
           }
         }
       }
       __syncthreads();
       for (int k = threadIdx.x; k < TW * TW; k += GT) {
-        const int ir = acci[0][k], ii = acci[1][k];
-        if (ir | ii) {
-          accf[0][k] += float(ir) * inv;
-          accf[1][k] += float(ii) * inv;
+        const unsigned long long w64 = acci[k];
+        if (w64) {
+          const int ir = static_cast<int>(static_cast<unsigned>(w64));
+          const int ii = static_cast<int>(static_cast<unsigned>((w64 - static_cast<unsigned long long>(
+                                                                          static_cast<long long>(ir))) >> 32));
+          const float2 a = accf[k];
+          accf[k] = make_float2(a.x + float(ir) * inv, a.y + float(ii) * inv);
         }
       }
       __syncthreads();
     }
     __syncthreads();
-    const int gy0 = ty * T - (KB_J / 2 - 1), gx0 = tx * T - (KB_J / 2 - 1);
+    float2* patch = halo + size_t(un.x) * TW * TW;
     for (int k = threadIdx.x; k < TW * TW; k += GT) {
-      const float re = accf[0][k], im = accf[1][k];
-      if (re != 0.f || im != 0.f) {
-        const int ly = k / TW, lx = k - ly * TW;
-        const int gy = (gy0 + ly) & (K - 1), gx = (gx0 + lx) & (K - 1);
-        float2* g = &grid[size_t(gy) * K + gx];
-        const float2 old = *g;
-        *g = make_float2(old.x + re, old.y + im);
+      const int ly = k / TW, lx = k - ly * TW;
+      const float2 a = accf[k];
+      const bool inside = ly >= R0 && ly < R0 + T && lx >= R0 && lx < R0 + T;
+      if (inside) {
+        if (a.x != 0.f || a.y != 0.f) {
+          float2* g = &grid[size_t(ty * T + ly - R0) * K + tx * T + lx - R0];
+          const float2 old = *g;
+          *g = make_float2(old.x + a.x, old.y + a.y);
+        }
+      } else {
+        patch[k] = a;
       }
     }
     __syncthreads();
   }
 }
 
-__global__ void k_build_active(const uint8_t* __restrict__ mask, int d, const int* __restrict__ item_off,
-                               int* __restrict__ list, int* __restrict__ count) {
-  int pos = 0;
-  for (int i = 0; i < d; ++i) {
-    if (mask == nullptr || mask[i] != 0) {
-      const int a = item_off[i], b = item_off[i + 1];
-      for (int t = threadIdx.x; t < b - a; t += blockDim.x) list[pos + t] = a + t;
-      pos += b - a;
+// Adds the halo patches of the eight neighbours of each tile into its interior cells
+// within reach of its edges (3 cells from the far edge, 4 from the near edge), clearing
+// every patch cell it reads.  Each patch cell outside its tile lies in exactly one other
+// tile's interior, so it has exactly one reader, and all patches are zero again when the
+// kernel ends (a tile not gridded in a launch therefore contributes nothing).
+template <int T>
+__global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, float2* __restrict__ grid,
+                                                  int K, int tpa) {
+  constexpr int TW = T + 8;
+  constexpr int R0 = KB_J / 2 - 1;
+  const int t = blockIdx.x;
+  const int ty = t / tpa, tx = t - (t / tpa) * tpa;
+  for (int k = threadIdx.x; k < T * T; k += GT) {
+    const int iy = k / T, ix = k - iy * T;
+    const bool edge_y = iy < KB_J / 2 || iy >= T - R0, edge_x = ix < KB_J / 2 || ix >= T - R0;
+    if (!edge_y && !edge_x) continue;
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (dy == 0 && dx == 0) continue;
+        // local coordinates of this cell in the neighbour's region
+        const int ly = iy - dy * T + R0, lx = ix - dx * T + R0;
+        if (ly < 0 || ly >= TW || lx < 0 || lx >= TW) continue;
+        const int nt = ((ty + dy + tpa) & (tpa - 1)) * tpa + ((tx + dx + tpa) & (tpa - 1));
+        float2* hp = &halo[size_t(nt) * TW * TW + ly * TW + lx];
+        const float2 h = *hp;
+        if (h.x != 0.f || h.y != 0.f) {
+          acc.x += h.x;
+          acc.y += h.y;
+          *hp = make_float2(0.f, 0.f);
+        }
+      }
+    if (acc.x != 0.f || acc.y != 0.f) {
+      float2* g = &grid[size_t(ty * T + iy) * K + tx * T + ix];
+      const float2 old = *g;
+      *g = make_float2(old.x + acc.x, old.y + acc.y);
     }
   }
-  if (threadIdx.x == 0) *count = pos;
+}
+
+__global__ __launch_bounds__(1024) void k_build_active(const uint8_t* __restrict__ mask, int d,
+                                                       const int* __restrict__ item_off,
+                                                       const Item* __restrict__ items, int n_items,
+                                                       int* __restrict__ list, int* __restrict__ count,
+                                                       int* __restrict__ dest) {
+  // dest[i]: first list position of block i's items (or -1 if inactive)
+  if (threadIdx.x == 0) {
+    int pos = 0;
+    for (int i = 0; i < d; ++i) {
+      const bool act = mask == nullptr || mask[i] != 0;
+      dest[i] = act ? pos : -1;
+      if (act) pos += item_off[i + 1] - item_off[i];
+    }
+    *count = pos;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n_items; k += blockDim.x) {
+    const int b = items[k].x;
+    const int base = dest[b];
+    if (base >= 0) list[base + k - item_off[b]] = k;
+  }
 }
 
 __global__ __launch_bounds__(GT) void k_block_sumsq(ItemSource src, const float2* __restrict__ y,
@@ -342,28 +404,26 @@ template <int T, int MODE>
 int launch_grid(const Plan& p, const int4* units, int nunits, const int* idx, const uint8_t* mask, float2* grid,
                 const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
                 hipStream_t s) {
-  if (nunits <= 0) return RI_OK;
-  hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GT), 0, s, units, nunits, idx,
-                     p.items, mask, p.coord, grid, p.K, p.tpa, p.poly, y, e, v, stats, eps);
+  if (nunits > 0) {
+    hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GT), 0, s, units, nunits, idx,
+                       p.items, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, stats, eps);
+    RI_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL((k_grid_halo<T>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
 
 template <int MODE>
-int grid_phases(const Plan& p, const int4* units, const int* off, const int* idx, const uint8_t* mask,
-                float2* grid, const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
-                hipStream_t s) {
-  for (int c = 0; c < 4; ++c) {
-    const int4* u = units + off[c];
-    const int n = off[c + 1] - off[c];
-    switch (p.tile) {
-      case 16: RI_TRY((launch_grid<16, MODE>(p, u, n, idx, mask, grid, y, e, v, stats, eps, s))); break;
-      case 32: RI_TRY((launch_grid<32, MODE>(p, u, n, idx, mask, grid, y, e, v, stats, eps, s))); break;
-      case 64: RI_TRY((launch_grid<64, MODE>(p, u, n, idx, mask, grid, y, e, v, stats, eps, s))); break;
-      default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
-    }
+int grid_units(const Plan& p, const int4* units, int nunits, const int* idx, const uint8_t* mask, float2* grid,
+               const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
+               hipStream_t s) {
+  switch (p.tile) {
+    case 16: return launch_grid<16, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s);
+    case 32: return launch_grid<32, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s);
+    case 64: return launch_grid<64, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s);
+    default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
   }
-  return RI_OK;
 }
 
 #define RI_TILE_DISPATCH(KERNEL, ...)                                                          \
@@ -377,8 +437,8 @@ int grid_phases(const Plan& p, const int4* units, const int* off, const int* idx
 }  // namespace
 
 int build_active(const Plan& p, const uint8_t* mask, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_active, dim3(1), dim3(256), 0, s, mask, p.d, p.item_off, p.active_list,
-                     p.active_count);
+  hipLaunchKernelGGL(k_build_active, dim3(1), dim3(1024), 0, s, mask, p.d, p.item_off, p.items, p.n_items,
+                     p.active_list, p.active_count, p.block_dest);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
@@ -423,25 +483,24 @@ int degrid_residual(const Plan& p, const float2* grid, const float2* y, const fl
 }
 
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s) {
-  return grid_phases<GR_APPLY>(p, p.units, p.phase_off_host, p.tile_items, mask, grid, y, nullptr, nullptr,
-                               nullptr, nullptr, s);
+  return grid_units<GR_APPLY>(p, p.units, p.n_units, p.tile_items, mask, grid, y, nullptr, nullptr, nullptr,
+                              nullptr, s);
 }
 
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s) {
-  return grid_phases<GR_APPLY>(p, p.units, p.phase_off_host, p.tile_items, nullptr, grid, v, nullptr, nullptr,
-                               nullptr, nullptr, s);
+  return grid_units<GR_APPLY>(p, p.units, p.n_units, p.tile_items, nullptr, grid, v, nullptr, nullptr, nullptr,
+                              nullptr, s);
 }
 
 int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
                  const uint8_t* mask, float2* grid, hipStream_t s) {
-  return grid_phases<GR_PROJECT>(p, p.units, p.phase_off_host, p.tile_items, mask, grid, nullptr, e, v, stats,
-                                 eps, s);
+  return grid_units<GR_PROJECT>(p, p.units, p.n_units, p.tile_items, mask, grid, nullptr, e, v, stats, eps, s);
 }
 
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const double* stats,
                        const double* eps, float2* grid, hipStream_t s) {
-  return grid_phases<GR_PROJECT>(p, p.bunits, &p.bunit_off_host[4 * block], p.iota, nullptr, grid, nullptr, e,
-                                 v, stats, eps, s);
+  const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
+  return grid_units<GR_PROJECT>(p, p.bunits + a, b - a, p.iota, nullptr, grid, nullptr, e, v, stats, eps, s);
 }
 
 }  // namespace ri

@@ -66,6 +66,8 @@ void destroy_plan(Plan& p) {
   dev_free(p.bunits);
   dev_free(p.item_part);
   dev_free(p.block_tmp);
+  dev_free(p.block_dest);
+  dev_free(p.halo);
   dev_free(p.active_count);
   dev_free(p.norm_tmp);
   dev_free(p.dsum);
@@ -174,29 +176,26 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   for (int t = 0; t < p.n_tiles; ++t) tile_cnt[t + 1] += tile_cnt[t];
   std::vector<int> tile_items(items.size()), fill(tile_cnt.begin(), tile_cnt.end() - 1);
   for (int k = 0; k < int(items.size()); ++k) tile_items[fill[items[k].y]++] = k;
-  auto colour = [&](int t) { return ((t / tpa) & 1) * 2 + ((t % tpa) & 1); };
   std::vector<int4> units, bunits;
-  for (int c = 0; c < 4; ++c) {
-    p.phase_off_host[c] = int(units.size());
+  {
     std::vector<int> ts;
     for (int t = 0; t < p.n_tiles; ++t)
-      if (tile_vis[t] > 0 && colour(t) == c) ts.push_back(t);
+      if (tile_vis[t] > 0) ts.push_back(t);
     std::stable_sort(ts.begin(), ts.end(), [&](int a, int b) { return tile_vis[a] > tile_vis[b]; });
     for (int t : ts) units.push_back(make_int4(t, tile_cnt[t], tile_cnt[t + 1], 0));
   }
-  p.phase_off_host[4] = int(units.size());
-  p.bunit_off_host.assign(4 * size_t(d) + 1, 0);
-  for (int i = 0; i < d; ++i)
-    for (int c = 0; c < 4; ++c) {
-      p.bunit_off_host[4 * i + c] = int(bunits.size());
-      for (int k = p.item_off_host[i]; k < p.item_off_host[i + 1];) {
-        int e = k;
-        while (e < p.item_off_host[i + 1] && items[e].y == items[k].y) ++e;
-        if (colour(items[k].y) == c) bunits.push_back(make_int4(items[k].y, k, e, 0));
-        k = e;
-      }
+  p.n_units = int(units.size());
+  p.bunit_off_host.assign(size_t(d) + 1, 0);
+  for (int i = 0; i < d; ++i) {
+    p.bunit_off_host[i] = int(bunits.size());
+    for (int k = p.item_off_host[i]; k < p.item_off_host[i + 1];) {
+      int e = k;
+      while (e < p.item_off_host[i + 1] && items[e].y == items[k].y) ++e;
+      bunits.push_back(make_int4(items[k].y, k, e, 0));
+      k = e;
     }
-  p.bunit_off_host[4 * d] = int(bunits.size());
+  }
+  p.bunit_off_host[d] = int(bunits.size());
   std::vector<int> iota(items.size());
   for (size_t k = 0; k < iota.size(); ++k) iota[k] = int(k);
 
@@ -223,6 +222,8 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.bunits, bunits.size()));
   RI_TRY(dev_alloc(&p.item_part, 2 * items.size()));
   RI_TRY(dev_alloc(&p.block_tmp, 2 * size_t(d)));
+  RI_TRY(dev_alloc(&p.block_dest, size_t(d)));
+  RI_TRY(dev_alloc(&p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8)));
   RI_TRY(dev_alloc(&p.active_count, 1));
   RI_TRY(dev_alloc(&p.norm_tmp, size_t(n) * n));
   RI_TRY(dev_alloc(&p.dsum, SUMSQ_SCRATCH));
@@ -236,6 +237,8 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_HIP(hipMemcpyAsync(p.units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.bunits, bunits.data(), bunits.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.scale, sc.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
+  // tiles without visibilities keep an all-zero halo patch forever
+  RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8), s));
   RI_HIP(hipStreamSynchronize(s));
   return RI_OK;
 }

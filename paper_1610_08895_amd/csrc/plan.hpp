@@ -38,10 +38,10 @@ struct Plan {
 
   std::vector<int> item_off_host;  // d + 1
   int n_tiles = 0;                  // tpa * tpa
-  // gridding units {tile, first, end} over an item index list, in four colour phases
-  // (colour (ty & 1) * 2 + (tx & 1)): all blocks together, and block by block
-  int phase_off_host[5] = {0};
-  std::vector<int> bunit_off_host;  // 4 d + 1
+  // gridding units {tile, first, end} over an item index list: all blocks together (densest
+  // tile first), and block by block
+  int n_units = 0;
+  std::vector<int> bunit_off_host;  // d + 1
   std::vector<int64_t> order_host;  // plan position -> user index
   std::vector<int64_t> block_off_host;
 
@@ -61,6 +61,8 @@ struct Plan {
   int4* bunits = nullptr;       // per block and colour; ranges into iota
   double* item_part = nullptr;  // 2 * n_items per-item partial sums of the block norms
   double* block_tmp = nullptr;  // 2 * d
+  int* block_dest = nullptr;    // d: active-list position of each block's first item
+  float2* halo = nullptr;       // n_tiles * (tile + 8)^2 halo patches of the gridding
   int* active_count = nullptr;
   float* norm_tmp = nullptr;  // n * n scratch for power iterations
   double* dsum = nullptr;     // FP64 reduction scratch

@@ -6,7 +6,8 @@
 //
 // Each workgroup owns an output tile and stages the input it needs in LDS together with
 // its periodic halo (filter length - 2 samples), then runs the row and the column filters
-// from LDS.  Analysis of level 1 reads x~ once per wavelet from L2; the dual update of step
+// from LDS; the filter length is a compile-time constant per basis.  Synthesis computes
+// output pairs (2q, 2q + 1) from the same coefficients a[q - u], d[q - u].  Analysis of level 1 reads x~ once per wavelet from L2; the dual update of step
 // 13, s = clip(s + Psi^dagger x~, -alpha, alpha), is applied as each coefficient is
 // produced.  The last synthesis level sums all bases in registers and applies steps 17-18
 // (primal update and extrapolation) in the same kernel.
@@ -25,11 +26,6 @@ constexpr int ST = 256;  // threads per workgroup
 constexpr int TO = 16;   // analysis: outputs per subband per axis per workgroup
 constexpr int TS = 32;   // synthesis: outputs per axis per workgroup
 
-__device__ __forceinline__ int pmod(int a, int m) {
-  const int r = a % m;
-  return r < 0 ? r + m : r;
-}
-
 __device__ __forceinline__ float clampf(float v, float a) { return fminf(fmaxf(v, -a), a); }
 
 struct DwtArgs {
@@ -46,28 +42,18 @@ __device__ __forceinline__ void put_coef(float* p, float v, int clip, float alph
   *p = clip ? clampf(*p + v, alpha) : v;
 }
 
-__global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, SaraFilters F) {
-  constexpr int RW = 2 * TO + MAX_TAPS - 2;
-  __shared__ float in[RW * RW];
-  __shared__ float lo[RW * TO], hi[RW * TO];
-  const int n = A.n, m = A.m, mo = A.m / 2;
-  const int i0 = blockIdx.y * TO, j0 = blockIdx.x * TO;
-  const int z = blockIdx.z;
-  if (z == A.nw) {  // Dirac basis at level 1: coefficient = pixel
-    for (int idx = threadIdx.x; idx < 4 * TO * TO; idx += ST) {
-      const int r = 2 * i0 + idx / (2 * TO), c = 2 * j0 + idx % (2 * TO);
-      if (r < n && c < n) put_coef(&A.s[size_t(r) * n + c], A.x[size_t(r) * n + c], A.clip, A.alpha);
-    }
-    return;
-  }
-  const int w = z;
-  const int L = F.len[w];
+// One analysis level for wavelet w with filters of (compile-time) length L on an output
+// tile (i0, j0) of each subband.  Sizes are powers of two, so indices wrap with masks.
+template <int L>
+__device__ __forceinline__ void analysis_tile(const DwtArgs& A, const SaraFilters& F, int w, int i0, int j0,
+                                              float* in, float* lo, float* hi) {
+  constexpr int RE = 2 * TO + L - 2;       // input rows / columns the tile reads
+  constexpr int RW = 2 * TO + MAX_TAPS - 2; // LDS row stride
+  const int n = A.n, m = A.m, mo = A.m / 2, mm = A.m - 1;
   const float* src = A.level == 1 ? A.x : A.tmp + w * A.tmp_stride + A.in_off;
-  const int RE = 2 * TO + L - 2;
   for (int idx = threadIdx.x; idx < RE * RE; idx += ST) {
     const int ly = idx / RE, lx = idx - ly * RE;
-    const int gy = (2 * i0 + ly) % m, gx = (2 * j0 + lx) % m;
-    in[ly * RW + lx] = src[size_t(gy) * m + gx];
+    in[ly * RW + lx] = src[size_t((2 * i0 + ly) & mm) * m + ((2 * j0 + lx) & mm)];
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < RE * TO; idx += ST) {
@@ -75,11 +61,10 @@ __global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, SaraFilters F) {
     const float* row = &in[rho * RW + 2 * j];
     float a = 0.f, d = 0.f;
 #pragma unroll
-    for (int t = 0; t < MAX_TAPS; ++t)
-      if (t < L) {
-        a = fmaf(F.h[w][t], row[t], a);
-        d = fmaf(F.g[w][t], row[t], d);
-      }
+    for (int t = 0; t < L; ++t) {
+      a = fmaf(F.h[w][t], row[t], a);
+      d = fmaf(F.g[w][t], row[t], d);
+    }
     lo[rho * TO + j] = a;
     hi[rho * TO + j] = d;
   }
@@ -91,20 +76,50 @@ __global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, SaraFilters F) {
     if (oi >= mo || oj >= mo) continue;
     float ll = 0.f, lh = 0.f, hl = 0.f, hh = 0.f;
 #pragma unroll
-    for (int t = 0; t < MAX_TAPS; ++t)
-      if (t < L) {
-        const float l = lo[(2 * i + t) * TO + j], h = hi[(2 * i + t) * TO + j];
-        ll = fmaf(F.h[w][t], l, ll);
-        lh = fmaf(F.h[w][t], h, lh);
-        hl = fmaf(F.g[w][t], l, hl);
-        hh = fmaf(F.g[w][t], h, hh);
-      }
+    for (int t = 0; t < L; ++t) {
+      const float l = lo[(2 * i + t) * TO + j], h = hi[(2 * i + t) * TO + j];
+      ll = fmaf(F.h[w][t], l, ll);
+      lh = fmaf(F.h[w][t], h, lh);
+      hl = fmaf(F.g[w][t], l, hl);
+      hh = fmaf(F.g[w][t], h, hh);
+    }
     if (A.level < A.levels) A.tmp[w * A.tmp_stride + A.out_off + size_t(oi) * mo + oj] = ll;
     else put_coef(&sb[size_t(oi) * n + oj], ll, A.clip, A.alpha);
     put_coef(&sb[size_t(oi) * n + mo + oj], lh, A.clip, A.alpha);
     put_coef(&sb[size_t(mo + oi) * n + oj], hl, A.clip, A.alpha);
     put_coef(&sb[size_t(mo + oi) * n + mo + oj], hh, A.clip, A.alpha);
   }
+}
+
+#define RI_SWITCH_L(LEN, CALL)          \
+  switch (LEN) {                        \
+    case 2: CALL(2); break;             \
+    case 4: CALL(4); break;             \
+    case 6: CALL(6); break;             \
+    case 8: CALL(8); break;             \
+    case 10: CALL(10); break;           \
+    case 12: CALL(12); break;           \
+    case 14: CALL(14); break;           \
+    default: CALL(16); break;           \
+  }
+
+__global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, SaraFilters F) {
+  constexpr int RW = 2 * TO + MAX_TAPS - 2;
+  __shared__ float in[RW * RW];
+  __shared__ float lo[RW * TO], hi[RW * TO];
+  const int n = A.n;
+  const int i0 = blockIdx.y * TO, j0 = blockIdx.x * TO;
+  const int z = blockIdx.z;
+  if (z == A.nw) {  // Dirac basis at level 1: coefficient = pixel
+    for (int idx = threadIdx.x; idx < 4 * TO * TO; idx += ST) {
+      const int r = 2 * i0 + idx / (2 * TO), c = 2 * j0 + idx % (2 * TO);
+      if (r < n && c < n) put_coef(&A.s[size_t(r) * n + c], A.x[size_t(r) * n + c], A.clip, A.alpha);
+    }
+    return;
+  }
+#define RI_ANALYSIS(LL) analysis_tile<LL>(A, F, z, i0, j0, in, lo, hi)
+  RI_SWITCH_L(F.len[z], RI_ANALYSIS)
+#undef RI_ANALYSIS
 }
 
 struct IdwtArgs {
@@ -119,111 +134,119 @@ struct IdwtArgs {
   float tau, sigma, varsigma;
 };
 
-// Loads the four level subbands around output tile (p0, q0) and runs the column (y)
-// synthesis into lx / hx; returns the filter length.
-template <int RS>
-__device__ __forceinline__ int synth_rows(const IdwtArgs& A, const SaraFilters& F, int w, int p0, int q0,
-                                          float (*sb)[RS * RS], float* lxs, float* hxs) {
-  const int n = A.n, mo = A.m / 2;
-  const int L = F.len[w];
-  const int RL = (TS + L) / 2;
-  const int kby = (p0 - L) / 2, kbx = (q0 - L) / 2;
+constexpr int RS = TS / 2 + MAX_TAPS / 2;  // LDS stride of a staged subband region
+
+// One synthesis level for wavelet w (filters of length L) on output tile (p0, q0):
+// out[2q + r] = sum_u h[2u + r] a[q - u] + g[2u + r] d[q - u] along each axis (the
+// transpose of the analysis), columns (y) first into lo / hi, then rows (x).  Returns
+// through `emit(pl, q, v_even, v_odd)` the output pairs (p0 + pl, q0 + 2q + {0, 1}).
+template <int L, class Emit>
+__device__ __forceinline__ void synthesis_tile(const IdwtArgs& A, const SaraFilters& F, int w, int p0, int q0,
+                                               float (*sb)[RS * RS], float* lo, float* hi, Emit& emit) {
+  constexpr int H = L / 2;
+  constexpr int RL = TS / 2 + H;  // coefficient rows / columns the tile reads
+  const int n = A.n, mo = A.m / 2, mk = A.m / 2 - 1;
+  const int kr = p0 / 2 - H, kc = q0 / 2 - H;
   const float* sw = A.s + size_t(w + A.dirac) * n * n;
   const bool ll_coef = A.level == A.levels;
   const float* ll = ll_coef ? sw : A.tmp + w * A.tmp_stride + A.ll_off;
   const int ll_stride = ll_coef ? n : mo;
-  for (int idx = threadIdx.x; idx < 4 * RL * RL; idx += ST) {
-    const int q = idx / (RL * RL), rem = idx - q * RL * RL;
-    const int ky = rem / RL, kx = rem - ky * RL;
-    const int gy = pmod(kby + ky, mo), gx = pmod(kbx + kx, mo);
-    float v;
-    if (q == 0) v = ll[size_t(gy) * ll_stride + gx];
-    else if (q == 1) v = sw[size_t(gy) * n + mo + gx];       // low-y, high-x
-    else if (q == 2) v = sw[size_t(mo + gy) * n + gx];       // high-y, low-x
-    else v = sw[size_t(mo + gy) * n + mo + gx];              // high-y, high-x
-    sb[q][ky * RS + kx] = v;
+  for (int idx = threadIdx.x; idx < RL * RL; idx += ST) {
+    const int ky = idx / RL, kx = idx - ky * RL;
+    const int gy = (kr + ky) & mk, gx = (kc + kx) & mk;
+    sb[0][ky * RS + kx] = ll[size_t(gy) * ll_stride + gx];
+    sb[1][ky * RS + kx] = sw[size_t(gy) * n + mo + gx];       // low-y, high-x
+    sb[2][ky * RS + kx] = sw[size_t(mo + gy) * n + gx];       // high-y, low-x
+    sb[3][ky * RS + kx] = sw[size_t(mo + gy) * n + mo + gx];  // high-y, high-x
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < TS * RL; idx += ST) {
-    const int pl = idx / RL, jl = idx - pl * RL;
-    float a = 0.f, b = 0.f;
+  for (int idx = threadIdx.x; idx < (TS / 2) * RL; idx += ST) {
+    const int qy = idx / RL, jl = idx - qy * RL;
+    float le = 0.f, lo_ = 0.f, he = 0.f, ho = 0.f;
 #pragma unroll
-    for (int t = 0; t < MAX_TAPS; ++t)
-      if (t < L && ((pl - t) & 1) == 0) {
-        const int kl = (pl - t + L) >> 1;
-        a = fmaf(F.h[w][t], sb[0][kl * RS + jl], a);
-        a = fmaf(F.g[w][t], sb[2][kl * RS + jl], a);
-        b = fmaf(F.h[w][t], sb[1][kl * RS + jl], b);
-        b = fmaf(F.g[w][t], sb[3][kl * RS + jl], b);
-      }
-    lxs[pl * RS + jl] = a;
-    hxs[pl * RS + jl] = b;
-  }
-  __syncthreads();
-  return L;
-}
-
-template <int RS>
-__device__ __forceinline__ float synth_cols(const SaraFilters& F, int w, int L, int pl, int ql, const float* lxs,
-                                            const float* hxs) {
-  float o = 0.f;
-#pragma unroll
-  for (int t = 0; t < MAX_TAPS; ++t)
-    if (t < L && ((ql - t) & 1) == 0) {
-      const int jl = (ql - t + L) >> 1;
-      o = fmaf(F.h[w][t], lxs[pl * RS + jl], o);
-      o = fmaf(F.g[w][t], hxs[pl * RS + jl], o);
+    for (int u = 0; u < H; ++u) {
+      const int k = (qy + H - u) * RS + jl;
+      const float a0 = sb[0][k], a1 = sb[1][k], a2 = sb[2][k], a3 = sb[3][k];
+      le = fmaf(F.h[w][2 * u], a0, fmaf(F.g[w][2 * u], a2, le));
+      lo_ = fmaf(F.h[w][2 * u + 1], a0, fmaf(F.g[w][2 * u + 1], a2, lo_));
+      he = fmaf(F.h[w][2 * u], a1, fmaf(F.g[w][2 * u], a3, he));
+      ho = fmaf(F.h[w][2 * u + 1], a1, fmaf(F.g[w][2 * u + 1], a3, ho));
     }
-  return o;
+    lo[(2 * qy) * RS + jl] = le;
+    lo[(2 * qy + 1) * RS + jl] = lo_;
+    hi[(2 * qy) * RS + jl] = he;
+    hi[(2 * qy + 1) * RS + jl] = ho;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < TS * TS / 2 / ST; ++k) {
+    const int idx = threadIdx.x + k * ST;
+    const int pl = idx / (TS / 2), qx = idx - pl * (TS / 2);
+    float ve = 0.f, vo = 0.f;
+#pragma unroll
+    for (int u = 0; u < H; ++u) {
+      const float a = lo[pl * RS + qx + H - u], d = hi[pl * RS + qx + H - u];
+      ve = fmaf(F.h[w][2 * u], a, fmaf(F.g[w][2 * u], d, ve));
+      vo = fmaf(F.h[w][2 * u + 1], a, fmaf(F.g[w][2 * u + 1], d, vo));
+    }
+    emit(k, pl, qx, ve, vo);
+  }
 }
 
 __global__ __launch_bounds__(ST) void k_idwt_level(IdwtArgs A, SaraFilters F) {
-  constexpr int RS = (TS + MAX_TAPS) / 2;
   __shared__ float sb[4][RS * RS];
-  __shared__ float lxs[TS * RS], hxs[TS * RS];
+  __shared__ float lo[TS * RS], hi[TS * RS];
   const int w = blockIdx.z;
   const int p0 = blockIdx.y * TS, q0 = blockIdx.x * TS, m = A.m;
-  const int L = synth_rows<RS>(A, F, w, p0, q0, sb, lxs, hxs);
   float* out = A.tmp + w * A.tmp_stride + A.out_off;
-  for (int idx = threadIdx.x; idx < TS * TS; idx += ST) {
-    const int pl = idx / TS, ql = idx - pl * TS;
-    if (p0 + pl < m && q0 + ql < m) out[size_t(p0 + pl) * m + q0 + ql] = synth_cols<RS>(F, w, L, pl, ql, lxs, hxs);
-  }
+  auto emit = [&](int, int pl, int qx, float ve, float vo) {
+    const int p = p0 + pl, q = q0 + 2 * qx;
+    if (p < m && q < m) {
+      out[size_t(p) * m + q] = ve;
+      out[size_t(p) * m + q + 1] = vo;
+    }
+  };
+#define RI_SYNTH(LL) synthesis_tile<LL>(A, F, w, p0, q0, sb, lo, hi, emit)
+  RI_SWITCH_L(F.len[w], RI_SYNTH)
+#undef RI_SYNTH
 }
 
 template <int MODE>
 __global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, SaraFilters F) {
-  constexpr int RS = (TS + MAX_TAPS) / 2;
-  constexpr int PER = TS * TS / ST;
+  constexpr int PER = TS * TS / 2 / ST;  // output pairs per thread
   __shared__ float sb[4][RS * RS];
-  __shared__ float lxs[TS * RS], hxs[TS * RS];
+  __shared__ float lo[TS * RS], hi[TS * RS];
   const int p0 = blockIdx.y * TS, q0 = blockIdx.x * TS, n = A.n;
-  float acc[PER];
+  float acc_e[PER], acc_o[PER];
 #pragma unroll
-  for (int k = 0; k < PER; ++k) acc[k] = 0.f;
+  for (int k = 0; k < PER; ++k) acc_e[k] = acc_o[k] = 0.f;
+  auto emit = [&](int k, int, int, float ve, float vo) {
+    acc_e[k] += ve;
+    acc_o[k] += vo;
+  };
   for (int w = 0; w < A.nw; ++w) {
-    const int L = synth_rows<RS>(A, F, w, p0, q0, sb, lxs, hxs);
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int idx = threadIdx.x + k * ST;
-      acc[k] += synth_cols<RS>(F, w, L, idx / TS, idx % TS, lxs, hxs);
-    }
+#define RI_SYNTH(LL) synthesis_tile<LL>(A, F, w, p0, q0, sb, lo, hi, emit)
+    RI_SWITCH_L(F.len[w], RI_SYNTH)
+#undef RI_SYNTH
     __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int idx = threadIdx.x + k * ST;
-    const int p = p0 + idx / TS, q = q0 + idx % TS;
+    const int p = p0 + idx / (TS / 2), q = q0 + 2 * (idx % (TS / 2));
     if (p >= n || q >= n) continue;
-    const size_t o = size_t(p) * n + q;
-    const float st = acc[k] + (A.dirac ? A.s[o] : 0.f);
-    if (MODE == 0) {
-      A.x[o] = st;
-    } else {
-      const float xo = A.x[o];
-      const float xn = fmaxf(0.f, xo - A.tau * (A.sigma * st + A.varsigma * A.g[o]));
-      A.x[o] = xn;
-      A.xt[o] = 2.f * xn - xo;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const size_t o = size_t(p) * n + q + r;
+      const float st = (r ? acc_o[k] : acc_e[k]) + (A.dirac ? A.s[o] : 0.f);
+      if (MODE == 0) {
+        A.x[o] = st;
+      } else {
+        const float xo = A.x[o];
+        const float xn = fmaxf(0.f, xo - A.tau * (A.sigma * st + A.varsigma * A.g[o]));
+        A.x[o] = xn;
+        A.xt[o] = 2.f * xn - xo;
+      }
     }
   }
 }
@@ -277,8 +300,8 @@ int create_sara(Sara& S, int n, int levels, uint32_t bases) {
   if (bases == 0) bases = 0x1FF;
   if (bases & ~0x1FFu) return fail(RI_EINVAL, "bases bitmask 0x%x has bits above db8", bases);
   if (levels < 1 || levels > 6) return fail(RI_EINVAL, "levels=%d must be in [1, 6]", levels);
-  if (n < 2 || n > 4096 || (n % (1 << levels)) != 0)
-    return fail(RI_EINVAL, "n=%d must be a multiple of 2^levels=%d and at most 4096", n, 1 << levels);
+  if (!is_pow2(n) || n > 4096 || n < (1 << levels) || n < 4)
+    return fail(RI_EINVAL, "n=%d must be a power of two in [max(4, 2^levels), 4096] (levels=%d)", n, levels);
   S.n = n;
   S.levels = levels;
   S.dirac = (bases & 1u) ? 1 : 0;
