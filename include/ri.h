@@ -81,7 +81,7 @@ typedef struct {
  * block_off_host: d+1 offsets, block i = rows [block_off[i], block_off[i+1]) (host);
  * every block must be nonempty.  J must be 8; beta <= 0 selects 2.34 J.  tune may be NULL.
  * Allocates device memory; synchronises `stream` before returning.
- * Errors: RI_EINVAL (n not a power of two in [16, 2048], M < 1, d < 1, empty block,
+ * Errors: RI_EINVAL (n not a power of two in [16, 2048], M < 1, d outside [1, 4096], empty block,
  * offsets not increasing, non-finite u-v), RI_ENOMEM, RI_EHIP.
  */
 int ri_plan_create(ri_plan* out, int n, int64_t M, const float* uv_host, int d,
@@ -203,7 +203,8 @@ enum {
 
 /* Enable (1) or disable (0) per-stage timing: while enabled, each ri_pd_step /
  * ri_pd_step_plain outside graph capture records a HIP event pair around every stage
- * on the stream that stage runs on.  Clears earlier records. */
+ * on the calling stream, and runs the sparsity branch on that stream too (instead of
+ * concurrently), so every stage is timed alone.  Clears earlier records. */
 int ri_pd_timing(ri_pd pd, int enable);
 /* Sum of the recorded durations (ms) and the number of records per stage, for the first
  * n stages; waits for the recorded events, then clears the records (host outputs). */

@@ -343,20 +343,43 @@ __global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, flo
   }
 }
 
+// Active work list: block i's items go to list positions dest[i] + (0, 1, ...), dest the
+// exclusive prefix sum of the active blocks' item counts (wave scans, d <= 64 * 64).
 __global__ __launch_bounds__(1024) void k_build_active(const uint8_t* __restrict__ mask, int d,
                                                        const int* __restrict__ item_off,
                                                        const Item* __restrict__ items, int n_items,
                                                        int* __restrict__ list, int* __restrict__ count,
                                                        int* __restrict__ dest) {
-  // dest[i]: first list position of block i's items (or -1 if inactive)
-  if (threadIdx.x == 0) {
-    int pos = 0;
-    for (int i = 0; i < d; ++i) {
-      const bool act = mask == nullptr || mask[i] != 0;
-      dest[i] = act ? pos : -1;
-      if (act) pos += item_off[i + 1] - item_off[i];
+  __shared__ int cnt[64 * 64];
+  __shared__ int chunk[64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  for (int c = wv; c < 64; c += nwv) {
+    const int i = c * 64 + lane;
+    int v = 0;
+    if (i < d && (mask == nullptr || mask[i] != 0)) v = item_off[i + 1] - item_off[i];
+    for (int off = 1; off < 64; off <<= 1) {  // inclusive scan within the wave
+      const int t = __shfl_up(v, off, 64);
+      if (lane >= off) v += t;
     }
-    *count = pos;
+    cnt[i] = v;
+    if (lane == 63) chunk[c] = v;
+  }
+  __syncthreads();
+  if (wv == 0) {
+    int v = chunk[lane];
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(v, off, 64);
+      if (lane >= off) v += t;
+    }
+    chunk[lane] = v;  // inclusive prefix of chunk totals
+    if (lane == 63) *count = v;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < d; i += blockDim.x) {
+    const bool act = mask == nullptr || mask[i] != 0;
+    const int c = i >> 6;
+    const int incl = cnt[i] + (c > 0 ? chunk[c - 1] : 0);
+    dest[i] = act ? incl - (item_off[i + 1] - item_off[i]) : -1;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < n_items; k += blockDim.x) {

@@ -77,7 +77,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
                 const ri_tuning* tune, hipStream_t s) {
   if (!is_pow2(n) || n < 16 || n > 2048) return fail(RI_EINVAL, "n=%d must be a power of two in [16, 2048]", n);
   if (M < 1 || M > (int64_t(1) << 31) - 1) return fail(RI_EINVAL, "M=%lld out of range", (long long)M);
-  if (d < 1) return fail(RI_EINVAL, "d=%d must be >= 1", d);
+  if (d < 1 || d > 4096) return fail(RI_EINVAL, "d=%d must be in [1, 4096]", d);
   if (!uv || !off) return fail(RI_EINVAL, "uv and block_off must not be NULL");
   if (J != KB_J) return fail(RI_EINVAL, "only J=%d is supported (got %d)", KB_J, J);
   if (off[0] != 0 || off[d] != M) return fail(RI_EINVAL, "block_off must start at 0 and end at M");

@@ -45,8 +45,9 @@ __device__ __forceinline__ void put_coef(float* p, float v, int clip, float alph
 // One analysis level for wavelet w with filters of (compile-time) length L on an output
 // tile (i0, j0) of each subband.  Sizes are powers of two, so indices wrap with masks.
 template <int L>
-__device__ __forceinline__ void analysis_tile(const DwtArgs& A, const SaraFilters& F, int w, int i0, int j0,
-                                              float* in, float* lo, float* hi) {
+__device__ __forceinline__ void analysis_tile(const DwtArgs& A, const float* __restrict__ hw, int w, int i0,
+                                              int j0, float* in, float* lo, float* hi) {
+  const float* __restrict__ gw = hw + MAX_TAPS;
   constexpr int RE = 2 * TO + L - 2;       // input rows / columns the tile reads
   constexpr int RW = 2 * TO + MAX_TAPS - 2; // LDS row stride
   const int n = A.n, m = A.m, mo = A.m / 2, mm = A.m - 1;
@@ -62,8 +63,8 @@ __device__ __forceinline__ void analysis_tile(const DwtArgs& A, const SaraFilter
     float a = 0.f, d = 0.f;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
-      a = fmaf(F.h[w][t], row[t], a);
-      d = fmaf(F.g[w][t], row[t], d);
+      a = fmaf(hw[t], row[t], a);
+      d = fmaf(gw[t], row[t], d);
     }
     lo[rho * TO + j] = a;
     hi[rho * TO + j] = d;
@@ -78,10 +79,10 @@ __device__ __forceinline__ void analysis_tile(const DwtArgs& A, const SaraFilter
 #pragma unroll
     for (int t = 0; t < L; ++t) {
       const float l = lo[(2 * i + t) * TO + j], h = hi[(2 * i + t) * TO + j];
-      ll = fmaf(F.h[w][t], l, ll);
-      lh = fmaf(F.h[w][t], h, lh);
-      hl = fmaf(F.g[w][t], l, hl);
-      hh = fmaf(F.g[w][t], h, hh);
+      ll = fmaf(hw[t], l, ll);
+      lh = fmaf(hw[t], h, lh);
+      hl = fmaf(gw[t], l, hl);
+      hh = fmaf(gw[t], h, hh);
     }
     if (A.level < A.levels) A.tmp[w * A.tmp_stride + A.out_off + size_t(oi) * mo + oj] = ll;
     else put_coef(&sb[size_t(oi) * n + oj], ll, A.clip, A.alpha);
@@ -103,7 +104,8 @@ __device__ __forceinline__ void analysis_tile(const DwtArgs& A, const SaraFilter
     default: CALL(16); break;           \
   }
 
-__global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, SaraFilters F) {
+__global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, const float* __restrict__ filt,
+                                                  const int* __restrict__ flen) {
   constexpr int RW = 2 * TO + MAX_TAPS - 2;
   __shared__ float in[RW * RW];
   __shared__ float lo[RW * TO], hi[RW * TO];
@@ -117,8 +119,8 @@ __global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, SaraFilters F) {
     }
     return;
   }
-#define RI_ANALYSIS(LL) analysis_tile<LL>(A, F, z, i0, j0, in, lo, hi)
-  RI_SWITCH_L(F.len[z], RI_ANALYSIS)
+#define RI_ANALYSIS(LL) analysis_tile<LL>(A, filt + z * FILT_STRIDE, z, i0, j0, in, lo, hi)
+  RI_SWITCH_L(flen[z], RI_ANALYSIS)
 #undef RI_ANALYSIS
 }
 
@@ -141,8 +143,9 @@ constexpr int RS = TS / 2 + MAX_TAPS / 2;  // LDS stride of a staged subband reg
 // transpose of the analysis), columns (y) first into lo / hi, then rows (x).  Returns
 // through `emit(pl, q, v_even, v_odd)` the output pairs (p0 + pl, q0 + 2q + {0, 1}).
 template <int L, class Emit>
-__device__ __forceinline__ void synthesis_tile(const IdwtArgs& A, const SaraFilters& F, int w, int p0, int q0,
-                                               float (*sb)[RS * RS], float* lo, float* hi, Emit& emit) {
+__device__ __forceinline__ void synthesis_tile(const IdwtArgs& A, const float* __restrict__ hw, int w, int p0,
+                                               int q0, float (*sb)[RS * RS], float* lo, float* hi, Emit& emit) {
+  const float* __restrict__ gw = hw + MAX_TAPS;
   constexpr int H = L / 2;
   constexpr int RL = TS / 2 + H;  // coefficient rows / columns the tile reads
   const int n = A.n, mo = A.m / 2, mk = A.m / 2 - 1;
@@ -167,10 +170,10 @@ __device__ __forceinline__ void synthesis_tile(const IdwtArgs& A, const SaraFilt
     for (int u = 0; u < H; ++u) {
       const int k = (qy + H - u) * RS + jl;
       const float a0 = sb[0][k], a1 = sb[1][k], a2 = sb[2][k], a3 = sb[3][k];
-      le = fmaf(F.h[w][2 * u], a0, fmaf(F.g[w][2 * u], a2, le));
-      lo_ = fmaf(F.h[w][2 * u + 1], a0, fmaf(F.g[w][2 * u + 1], a2, lo_));
-      he = fmaf(F.h[w][2 * u], a1, fmaf(F.g[w][2 * u], a3, he));
-      ho = fmaf(F.h[w][2 * u + 1], a1, fmaf(F.g[w][2 * u + 1], a3, ho));
+      le = fmaf(hw[2 * u], a0, fmaf(gw[2 * u], a2, le));
+      lo_ = fmaf(hw[2 * u + 1], a0, fmaf(gw[2 * u + 1], a2, lo_));
+      he = fmaf(hw[2 * u], a1, fmaf(gw[2 * u], a3, he));
+      ho = fmaf(hw[2 * u + 1], a1, fmaf(gw[2 * u + 1], a3, ho));
     }
     lo[(2 * qy) * RS + jl] = le;
     lo[(2 * qy + 1) * RS + jl] = lo_;
@@ -186,14 +189,15 @@ __device__ __forceinline__ void synthesis_tile(const IdwtArgs& A, const SaraFilt
 #pragma unroll
     for (int u = 0; u < H; ++u) {
       const float a = lo[pl * RS + qx + H - u], d = hi[pl * RS + qx + H - u];
-      ve = fmaf(F.h[w][2 * u], a, fmaf(F.g[w][2 * u], d, ve));
-      vo = fmaf(F.h[w][2 * u + 1], a, fmaf(F.g[w][2 * u + 1], d, vo));
+      ve = fmaf(hw[2 * u], a, fmaf(gw[2 * u], d, ve));
+      vo = fmaf(hw[2 * u + 1], a, fmaf(gw[2 * u + 1], d, vo));
     }
     emit(k, pl, qx, ve, vo);
   }
 }
 
-__global__ __launch_bounds__(ST) void k_idwt_level(IdwtArgs A, SaraFilters F) {
+__global__ __launch_bounds__(ST) void k_idwt_level(IdwtArgs A, const float* __restrict__ filt,
+                                                   const int* __restrict__ flen) {
   __shared__ float sb[4][RS * RS];
   __shared__ float lo[TS * RS], hi[TS * RS];
   const int w = blockIdx.z;
@@ -206,13 +210,14 @@ __global__ __launch_bounds__(ST) void k_idwt_level(IdwtArgs A, SaraFilters F) {
       out[size_t(p) * m + q + 1] = vo;
     }
   };
-#define RI_SYNTH(LL) synthesis_tile<LL>(A, F, w, p0, q0, sb, lo, hi, emit)
-  RI_SWITCH_L(F.len[w], RI_SYNTH)
+#define RI_SYNTH(LL) synthesis_tile<LL>(A, filt + w * FILT_STRIDE, w, p0, q0, sb, lo, hi, emit)
+  RI_SWITCH_L(flen[w], RI_SYNTH)
 #undef RI_SYNTH
 }
 
 template <int MODE>
-__global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, SaraFilters F) {
+__global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, const float* __restrict__ filt,
+                                                 const int* __restrict__ flen) {
   constexpr int PER = TS * TS / 2 / ST;  // output pairs per thread
   __shared__ float sb[4][RS * RS];
   __shared__ float lo[TS * RS], hi[TS * RS];
@@ -225,8 +230,8 @@ __global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, SaraFilters F) {
     acc_o[k] += vo;
   };
   for (int w = 0; w < A.nw; ++w) {
-#define RI_SYNTH(LL) synthesis_tile<LL>(A, F, w, p0, q0, sb, lo, hi, emit)
-    RI_SWITCH_L(F.len[w], RI_SYNTH)
+#define RI_SYNTH(LL) synthesis_tile<LL>(A, filt + w * FILT_STRIDE, w, p0, q0, sb, lo, hi, emit)
+    RI_SWITCH_L(flen[w], RI_SYNTH)
 #undef RI_SYNTH
     __syncthreads();
   }
@@ -260,7 +265,8 @@ int analysis(const Sara& S, const float* x, float* s, bool clip, float alpha, hi
               s, S.n, m, lev, S.levels, S.dirac, S.nw, clip ? 1 : 0, alpha};
     const int z = S.nw + ((lev == 1 && S.dirac) ? 1 : 0);
     if (z == 0) continue;
-    hipLaunchKernelGGL(k_dwt_level, dim3(tiles(mo, TO), tiles(mo, TO), z), dim3(ST), 0, st, A, S.filt);
+    hipLaunchKernelGGL(k_dwt_level, dim3(tiles(mo, TO), tiles(mo, TO), z), dim3(ST), 0, st, A, S.dfilt,
+                       S.dlen);
     RI_LAUNCH_CHECK();
   }
   return RI_OK;
@@ -272,7 +278,8 @@ int synthesis_lower(const Sara& S, const float* s, hipStream_t st) {
     IdwtArgs A{s, S.tmp, S.tmp_stride, lev < S.levels ? S.tmp_off[lev] : 0, S.tmp_off[lev - 1], S.n, m, lev,
                S.levels, S.dirac, S.nw, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f};
     if (S.nw == 0) break;
-    hipLaunchKernelGGL(k_idwt_level, dim3(tiles(m, TS), tiles(m, TS), S.nw), dim3(ST), 0, st, A, S.filt);
+    hipLaunchKernelGGL(k_idwt_level, dim3(tiles(m, TS), tiles(m, TS), S.nw), dim3(ST), 0, st, A, S.dfilt,
+                       S.dlen);
     RI_LAUNCH_CHECK();
   }
   return RI_OK;
@@ -283,8 +290,8 @@ int synthesis_top(const Sara& S, const float* s, const PrimalUpdate* u, float* x
              u ? u->x : x, u ? u->g : nullptr, u ? u->xt : nullptr, u ? u->tau : 0.f, u ? u->sigma : 0.f,
              u ? u->varsigma : 0.f};
   const dim3 g(tiles(S.n, TS), tiles(S.n, TS));
-  if (u) hipLaunchKernelGGL(k_idwt_top<1>, g, dim3(ST), 0, st, A, S.filt);
-  else hipLaunchKernelGGL(k_idwt_top<0>, g, dim3(ST), 0, st, A, S.filt);
+  if (u) hipLaunchKernelGGL(k_idwt_top<1>, g, dim3(ST), 0, st, A, S.dfilt, S.dlen);
+  else hipLaunchKernelGGL(k_idwt_top<0>, g, dim3(ST), 0, st, A, S.dfilt, S.dlen);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
@@ -294,6 +301,8 @@ void destroy_sara(Sara& S) {
   dev_free(S.coef_tmp);
   dev_free(S.vec_tmp);
   dev_free(S.dsum);
+  dev_free(S.dfilt);
+  dev_free(S.dlen);
 }
 
 int create_sara(Sara& S, int n, int levels, uint32_t bases) {
@@ -329,6 +338,18 @@ int create_sara(Sara& S, int n, int levels, uint32_t bases) {
   RI_TRY(dev_alloc(&S.coef_tmp, size_t(S.b) * n * n));
   RI_TRY(dev_alloc(&S.vec_tmp, size_t(n) * n));
   RI_TRY(dev_alloc(&S.dsum, SUMSQ_SCRATCH));
+  if (S.nw > 0) {
+    std::vector<float> f(size_t(S.nw) * FILT_STRIDE, 0.f);
+    for (int w = 0; w < S.nw; ++w)
+      for (int j = 0; j < MAX_TAPS; ++j) {
+        f[size_t(w) * FILT_STRIDE + j] = S.filt.h[w][j];
+        f[size_t(w) * FILT_STRIDE + MAX_TAPS + j] = S.filt.g[w][j];
+      }
+    RI_TRY(dev_alloc(&S.dfilt, f.size()));
+    RI_TRY(dev_alloc(&S.dlen, size_t(S.nw)));
+    RI_HIP(hipMemcpy(S.dfilt, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    RI_HIP(hipMemcpy(S.dlen, S.filt.len, S.nw * sizeof(int), hipMemcpyHostToDevice));
+  }
   return RI_OK;
 }
 

@@ -8,7 +8,10 @@ namespace ri {
 constexpr int MAX_WAVELETS = 8;
 constexpr int MAX_TAPS = 16;  // db8
 
-// Filters of the wavelet bases, by wavelet slot (kernel argument, read with scalar loads).
+// Filters of the wavelet bases, by wavelet slot.  On the device they live in one buffer,
+// FILT_STRIDE floats per slot (lowpass h in [0, 16), highpass g in [16, 32)), read through
+// a pointer with uniform indices (scalar loads).
+constexpr int FILT_STRIDE = 2 * MAX_TAPS;
 struct SaraFilters {
   float h[MAX_WAVELETS][MAX_TAPS];
   float g[MAX_WAVELETS][MAX_TAPS];
@@ -21,6 +24,8 @@ struct Sara {
   int nw = 0;     // number of wavelet bases
   int b = 0;      // dirac + nw
   SaraFilters filt{};
+  float* dfilt = nullptr;  // nw * FILT_STRIDE
+  int* dlen = nullptr;     // nw
   size_t tmp_stride = 0;        // floats of LL scratch per wavelet
   size_t tmp_off[8] = {0};      // offset of LL_l (l = 1..levels-1) inside a wavelet's scratch
   float* tmp = nullptr;         // nw * tmp_stride
