@@ -426,25 +426,27 @@ int wgs_for(const Plan& p, int units) {
 template <int T, int MODE>
 int launch_grid(const Plan& p, const int4* units, int nunits, const int* idx, const uint8_t* mask, float2* grid,
                 const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
-                hipStream_t s) {
+                hipStream_t s, bool with_halo = true) {
   if (nunits > 0) {
     hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GT), 0, s, units, nunits, idx,
                        p.items, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, stats, eps);
     RI_LAUNCH_CHECK();
   }
-  hipLaunchKernelGGL((k_grid_halo<T>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa);
-  RI_LAUNCH_CHECK();
+  if (with_halo) {
+    hipLaunchKernelGGL((k_grid_halo<T>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa);
+    RI_LAUNCH_CHECK();
+  }
   return RI_OK;
 }
 
 template <int MODE>
 int grid_units(const Plan& p, const int4* units, int nunits, const int* idx, const uint8_t* mask, float2* grid,
                const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
-               hipStream_t s) {
+               hipStream_t s, bool with_halo = true) {
   switch (p.tile) {
-    case 16: return launch_grid<16, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s);
-    case 32: return launch_grid<32, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s);
-    case 64: return launch_grid<64, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s);
+    case 16: return launch_grid<16, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s, with_halo);
+    case 32: return launch_grid<32, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s, with_halo);
+    case 64: return launch_grid<64, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s, with_halo);
     default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
   }
 }
@@ -517,7 +519,19 @@ int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s) {
 
 int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
                  const uint8_t* mask, float2* grid, hipStream_t s) {
-  return grid_units<GR_PROJECT>(p, p.units, p.n_units, p.tile_items, mask, grid, nullptr, e, v, stats, eps, s);
+  return grid_units<GR_PROJECT>(p, p.units, p.n_units, p.tile_items, mask, grid, nullptr, e, v, stats, eps, s,
+                                false);
+}
+
+int grid_halo(const Plan& p, float2* grid, hipStream_t s) {
+  switch (p.tile) {
+    case 16: hipLaunchKernelGGL((k_grid_halo<16>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa); break;
+    case 32: hipLaunchKernelGGL((k_grid_halo<32>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa); break;
+    case 64: hipLaunchKernelGGL((k_grid_halo<64>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa); break;
+    default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
+  }
+  RI_LAUNCH_CHECK();
+  return RI_OK;
 }
 
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const double* stats,

@@ -95,9 +95,11 @@ int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
                     const int* list, const int* count, int base, int count_host, hipStream_t s);
 // PD projection pass: v_new = (v + e) max(0, 1 - eps/||r||); grid += G^dagger (v_new - v); v = v_new,
-// for the active blocks (all tiles, four colour launches) or for one block.
+// for the active blocks (tile interiors; grid_halo must follow) or for one block (complete).
 int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
                  const uint8_t* mask, float2* grid, hipStream_t s);
+// Adds the tile halos left by grid_project (which stores them) into the grid.
+int grid_halo(const Plan& p, float2* grid, hipStream_t s);
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const double* stats,
                        const double* eps, float2* grid, hipStream_t s);
 // grid += G^dagger v over all items (used to rebuild the running sum from scratch).
