@@ -36,7 +36,8 @@ WORKLOAD = "n1024_m4m_d64"
 # the kernel each timed stage launches in the batched step
 STAGE_KERNEL = {
     "fft_rows": "k_fwd_rows<2048, 1, 256>", "fft_cols": "k_fwd_cols<2048, 8, 512>",
-    "degrid": "k_degrid<32, 1>", "grid": "k_grid_tiles<32, 1>", "grid_halo": "k_grid_halo<32>",
+    "degrid": "k_degrid<32, 1>", "block_norms": "k_block_stats", "grid": "k_grid_tiles<32, 1>",
+    "grid_halo": "k_grid_halo<32>",
     "ifft_cols": "k_adj_cols<2048, 8, 512>", "ifft_rows": "k_adj_rows<2048, 1, 256>",
     "psi_adj": "k_dwt_level (4 launches)", "psi_synth": "k_idwt_level (3 launches)", "update": "k_idwt_top<1>",
 }

@@ -188,20 +188,18 @@ int ri_pd_refresh(ri_pd pd, hipStream_t stream);
 /* Stages of one iteration, for per-stage timing (each stage is one kernel launch in the
  * batched step; the plain step times all per-block launches of a stage together). */
 enum {
-  RI_STAGE_ACTIVE = 0,      /* active-set work list (step 3)                               */
-  RI_STAGE_FFT_ROWS = 1,    /* F Z x~, row pass (step 4)                                    */
-  RI_STAGE_FFT_COLS = 2,    /* F Z x~, column pass (step 4)                                 */
-  RI_STAGE_DEGRID = 3,      /* G_i b_i, residuals, FP64 partial norms (steps 5, 8)          */
-  RI_STAGE_BLOCK_NORMS = 4, /* per-block reduction of the partial norms                     */
-  RI_STAGE_GRID = 5,        /* l2-ball shrink, G_i^dagger update, tile interiors (8, 9, 11) */
-  RI_STAGE_GRID_HALO = 6,   /* tile halos of the G_i^dagger update                         */
-  RI_STAGE_IFFT_COLS = 7,   /* Z^dagger F^dagger, column pass (step 17)                     */
-  RI_STAGE_IFFT_ROWS = 8,   /* Z^dagger F^dagger, row pass (step 17)                        */
-  RI_STAGE_STATS = 9,       /* export of the block statistics                              */
-  RI_STAGE_PSI_ADJ = 10,    /* Psi^dagger x~ and dual clip, all levels (step 13)            */
-  RI_STAGE_PSI_SYNTH = 11,  /* Psi s, every level but the finest (step 14)                  */
-  RI_STAGE_UPDATE = 12,     /* finest level of Psi s + steps 17-18                         */
-  RI_STAGE_COUNT = 13
+  RI_STAGE_FFT_ROWS = 0,    /* F Z x~, row pass (step 4)                                    */
+  RI_STAGE_FFT_COLS = 1,    /* F Z x~, column pass (step 4)                                 */
+  RI_STAGE_DEGRID = 2,      /* G_i b_i, residuals, FP64 partial norms (steps 5, 8)          */
+  RI_STAGE_BLOCK_NORMS = 3, /* per-block reduction of the partial norms, statistics out     */
+  RI_STAGE_GRID = 4,        /* l2-ball shrink, G_i^dagger update, tile interiors (8, 9, 11) */
+  RI_STAGE_GRID_HALO = 5,   /* tile halos of the G_i^dagger update                         */
+  RI_STAGE_IFFT_COLS = 6,   /* Z^dagger F^dagger, column pass (step 17)                     */
+  RI_STAGE_IFFT_ROWS = 7,   /* Z^dagger F^dagger, row pass (step 17)                        */
+  RI_STAGE_PSI_ADJ = 8,     /* Psi^dagger x~ and dual clip, all levels (step 13)            */
+  RI_STAGE_PSI_SYNTH = 9,   /* Psi s, every level but the finest (step 14)                  */
+  RI_STAGE_UPDATE = 10,     /* finest level of Psi s + steps 17-18                         */
+  RI_STAGE_COUNT = 11
 };
 
 /* Enable (1) or disable (0) per-stage timing: while enabled, each ri_pd_step /

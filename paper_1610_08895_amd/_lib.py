@@ -13,8 +13,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libri.so")
 
 RI_OK, RI_EINVAL, RI_ENOMEM, RI_EHIP, RI_ESTATE = 0, -1, -2, -3, -4
 RI_PD_X, RI_PD_XTILDE, RI_PD_S, RI_PD_V, RI_PD_ITER = range(5)
-STAGES = ("active", "fft_rows", "fft_cols", "degrid", "block_norms", "grid", "grid_halo", "ifft_cols",
-          "ifft_rows", "stats", "psi_adj", "psi_synth", "update")
+STAGES = ("fft_rows", "fft_cols", "degrid", "block_norms", "grid", "grid_halo", "ifft_cols", "ifft_rows",
+          "psi_adj", "psi_synth", "update")
 
 c_void_p, c_int, c_int64, c_double, c_size_t, c_uint32 = (
     ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t, ctypes.c_uint32)

@@ -13,7 +13,9 @@
 // Visibilities are sorted by (block, tile, cell); a work item holds up to `bin`
 // visibilities of one block in one T x T grid tile.
 //
-// Degridding walks the active items with a persistent grid of workgroups; each stages
+// Degridding walks the items with a persistent grid of workgroups, skipping the items
+// of inactive blocks (the mask is read on the device, so a captured graph follows
+// whatever mask is current); each stages
 // its tile plus the kernel's reach (3 cells before, 4 after, per axis) in LDS so all 64
 // taps of a visibility are LDS reads.  Block norms are accumulated per item in FP64 and
 // reduced per block by a second kernel in a fixed order (no atomics, deterministic).
@@ -34,7 +36,8 @@ namespace ri {
 
 namespace {
 
-constexpr int GT = 256;  // threads per workgroup
+constexpr int GT = 256;    // threads per workgroup
+constexpr int GGT = 1024;  // threads per workgroup of the tile gridding (a dense tile fills a CU)
 
 __device__ __forceinline__ void kb_weights(unsigned packed, const KBPoly& P, float* w, int& cell) {
   cell = int(packed >> FRAC_BITS);
@@ -54,13 +57,12 @@ __device__ __forceinline__ void kb_weights(unsigned packed, const KBPoly& P, flo
   }
 }
 
+// Items base .. base + count - 1, of which those whose block has mask[block] == 0 are
+// skipped (mask may be null).
 struct ItemSource {
   const Item* items;
-  const int* list;   // active item list, or nullptr for a contiguous range
-  const int* count;  // device count of `list`
-  int base, count_host;
-  __device__ __forceinline__ int n() const { return list ? *count : count_host; }
-  __device__ __forceinline__ int index(int a) const { return list ? list[a] : base + a; }
+  const uint8_t* mask;
+  int base, count;
 };
 
 enum { DG_APPLY = 0, DG_RESIDUAL = 1 };
@@ -73,10 +75,10 @@ __global__ __launch_bounds__(GT) void k_degrid(ItemSource src, const uint2* __re
   constexpr int TW = T + 8;
   __shared__ float2 tile[TW * TW];
   __shared__ double red[2][GT / 64];
-  const int nitems = src.n();
-  for (int a = blockIdx.x; a < nitems; a += gridDim.x) {
-    const int iidx = src.index(a);
+  for (int a = blockIdx.x; a < src.count; a += gridDim.x) {
+    const int iidx = src.base + a;
     const Item it = src.items[iidx];
+    if (src.mask != nullptr && src.mask[it.x] == 0) continue;
     const int ty = it.y / tpa, tx = it.y - (it.y / tpa) * tpa;
     const int gy0 = ty * T - (KB_J / 2 - 1), gx0 = tx * T - (KB_J / 2 - 1);
     for (int idx = threadIdx.x; idx < TW * TW; idx += GT) {
@@ -143,12 +145,20 @@ __global__ __launch_bounds__(GT) void k_degrid(ItemSource src, const uint2* __re
   }
 }
 
-// stats[2i], stats[2i+1] = sums of the per-item partials of block i, for active blocks.
+// stats[2i], stats[2i+1] = sums of the per-item partials of block i, for active blocks;
+// a copy goes to out (if not null), with NaN for inactive blocks.
 __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ mask, const int* __restrict__ item_off,
-                                                    const double* __restrict__ part, double* __restrict__ stats) {
+                                                    const double* __restrict__ part, double* __restrict__ stats,
+                                                    double* __restrict__ out) {
   __shared__ double red[2][GT / 64];
   const int i = blockIdx.x;
-  if (mask != nullptr && mask[i] == 0) return;
+  if (mask != nullptr && mask[i] == 0) {
+    if (out != nullptr && threadIdx.x == 0) {
+      out[2 * i] = __builtin_nan("");
+      out[2 * i + 1] = __builtin_nan("");
+    }
+    return;
+  }
   double a0 = 0.0, a1 = 0.0;
   for (int k = item_off[i] + threadIdx.x; k < item_off[i + 1]; k += GT) {
     a0 += part[2 * k];
@@ -169,6 +179,10 @@ __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ 
     }
     stats[2 * i] = s0;
     stats[2 * i + 1] = s1;
+    if (out != nullptr) {
+      out[2 * i] = s0;
+      out[2 * i + 1] = s1;
+    }
   }
 }
 
@@ -187,7 +201,7 @@ enum { GR_APPLY = 0, GR_PROJECT = 1 };
 // item.  At the end the tile interior (owned by this workgroup alone) is added to the grid
 // and the reach outside it is stored in the tile's halo patch for k_grid_halo.
 template <int T, int MODE>
-__global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ units, int nunits,
+__global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ units, int nunits,
                                                    const int* __restrict__ idx_list, const Item* __restrict__ items,
                                                    const uint8_t* __restrict__ mask, const uint2* __restrict__ coord,
                                                    float2* __restrict__ grid, float2* __restrict__ halo, int K,
@@ -199,12 +213,12 @@ __global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ unit
   __shared__ float2 accf[TW * TW];
   __shared__ unsigned long long acci[TW * TW];
   __shared__ float2 vals[MAX_BIN];
-  __shared__ float red[GT / 64];
+  __shared__ float red[GGT / 64];
   const int lane = threadIdx.x & 63;
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int4 un = units[u];
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
-    for (int k = threadIdx.x; k < TW * TW; k += GT) accf[k] = make_float2(0.f, 0.f);
+    for (int k = threadIdx.x; k < TW * TW; k += GGT) accf[k] = make_float2(0.f, 0.f);
     for (int q = un.y; q < un.z; ++q) {
       const Item it = items[idx_list[q]];
       if (mask != nullptr && mask[it.x] == 0) continue;
@@ -215,7 +229,7 @@ __global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ unit
       }
       // values (and the dual update of step 8), and the bound sum |Re| + |Im|
       float babs = 0.f;
-      for (int s = threadIdx.x; s < it.w; s += GT) {
+      for (int s = threadIdx.x; s < it.w; s += GGT) {
         const int m = it.z + s;
         float2 val;
         if (MODE == GR_APPLY) {
@@ -231,11 +245,11 @@ __global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ unit
       }
       for (int off = 32; off > 0; off >>= 1) babs += __shfl_xor(babs, off, 64);
       if (lane == 0) red[threadIdx.x / 64] = babs;
-      for (int k = threadIdx.x; k < TW * TW; k += GT) acci[k] = 0ull;
+      for (int k = threadIdx.x; k < TW * TW; k += GGT) acci[k] = 0ull;
       __syncthreads();
       float bound = 0.f;
 #pragma unroll
-      for (int k = 0; k < GT / 64; ++k) bound += red[k];
+      for (int k = 0; k < GGT / 64; ++k) bound += red[k];
       if (bound == 0.f) {  // the item changes nothing
         __syncthreads();
         continue;
@@ -245,7 +259,7 @@ __global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ unit
       frexpf(bound * 1.0001f, &ex);
       const float scale = ldexpf(1.f, 30 - ex), inv = ldexpf(1.f, ex - 30);
       const int S = (it.w + 63) >> 6;  // visibilities per lane slot
-      for (int j = threadIdx.x; j < 64 * S; j += GT) {
+      for (int j = threadIdx.x; j < 64 * S; j += GGT) {
         const int s = lane * S + (j >> 6);
         if (s >= it.w) continue;
         const uint2 c = coord[it.z + s];
@@ -269,7 +283,7 @@ __global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ unit
         }
       }
       __syncthreads();
-      for (int k = threadIdx.x; k < TW * TW; k += GT) {
+      for (int k = threadIdx.x; k < TW * TW; k += GGT) {
         const unsigned long long w64 = acci[k];
         if (w64) {
           const int ir = static_cast<int>(static_cast<unsigned>(w64));
@@ -283,7 +297,7 @@ __global__ __launch_bounds__(GT) void k_grid_tiles(const int4* __restrict__ unit
     }
     __syncthreads();
     float2* patch = halo + size_t(un.x) * TW * TW;
-    for (int k = threadIdx.x; k < TW * TW; k += GT) {
+    for (int k = threadIdx.x; k < TW * TW; k += GGT) {
       const int ly = k / TW, lx = k - ly * TW;
       const float2 a = accf[k];
       const bool inside = ly >= R0 && ly < R0 + T && lx >= R0 && lx < R0 + T;
@@ -343,58 +357,11 @@ __global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, flo
   }
 }
 
-// Active work list: block i's items go to list positions dest[i] + (0, 1, ...), dest the
-// exclusive prefix sum of the active blocks' item counts (wave scans, d <= 64 * 64).
-__global__ __launch_bounds__(1024) void k_build_active(const uint8_t* __restrict__ mask, int d,
-                                                       const int* __restrict__ item_off,
-                                                       const Item* __restrict__ items, int n_items,
-                                                       int* __restrict__ list, int* __restrict__ count,
-                                                       int* __restrict__ dest) {
-  __shared__ int cnt[64 * 64];
-  __shared__ int chunk[64];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-  for (int c = wv; c < 64; c += nwv) {
-    const int i = c * 64 + lane;
-    int v = 0;
-    if (i < d && (mask == nullptr || mask[i] != 0)) v = item_off[i + 1] - item_off[i];
-    for (int off = 1; off < 64; off <<= 1) {  // inclusive scan within the wave
-      const int t = __shfl_up(v, off, 64);
-      if (lane >= off) v += t;
-    }
-    cnt[i] = v;
-    if (lane == 63) chunk[c] = v;
-  }
-  __syncthreads();
-  if (wv == 0) {
-    int v = chunk[lane];
-    for (int off = 1; off < 64; off <<= 1) {
-      const int t = __shfl_up(v, off, 64);
-      if (lane >= off) v += t;
-    }
-    chunk[lane] = v;  // inclusive prefix of chunk totals
-    if (lane == 63) *count = v;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < d; i += blockDim.x) {
-    const bool act = mask == nullptr || mask[i] != 0;
-    const int c = i >> 6;
-    const int incl = cnt[i] + (c > 0 ? chunk[c - 1] : 0);
-    dest[i] = act ? incl - (item_off[i + 1] - item_off[i]) : -1;
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < n_items; k += blockDim.x) {
-    const int b = items[k].x;
-    const int base = dest[b];
-    if (base >= 0) list[base + k - item_off[b]] = k;
-  }
-}
-
 __global__ __launch_bounds__(GT) void k_block_sumsq(ItemSource src, const float2* __restrict__ y,
                                                     double* __restrict__ part) {
   __shared__ double red[GT / 64];
-  const int nitems = src.n();
-  for (int a = blockIdx.x; a < nitems; a += gridDim.x) {
-    const int iidx = src.index(a);
+  for (int a = blockIdx.x; a < src.count; a += gridDim.x) {
+    const int iidx = src.base + a;
     const Item it = src.items[iidx];
     double acc = 0.0;
     for (int m = it.z + threadIdx.x; m < it.z + it.w; m += GT) {
@@ -428,7 +395,8 @@ int launch_grid(const Plan& p, const int4* units, int nunits, const int* idx, co
                 const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
                 hipStream_t s, bool with_halo = true) {
   if (nunits > 0) {
-    hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GT), 0, s, units, nunits, idx,
+    const int g = p.persistent_wgs > 0 ? p.persistent_wgs : device_cus() * 2;
+    hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(nunits < g ? nunits : g), dim3(GGT), 0, s, units, nunits, idx,
                        p.items, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, stats, eps);
     RI_LAUNCH_CHECK();
   }
@@ -461,33 +429,26 @@ int grid_units(const Plan& p, const int4* units, int nunits, const int* idx, con
 
 }  // namespace
 
-int build_active(const Plan& p, const uint8_t* mask, hipStream_t s) {
-  hipLaunchKernelGGL(k_build_active, dim3(1), dim3(1024), 0, s, mask, p.d, p.item_off, p.items, p.n_items,
-                     p.active_list, p.active_count, p.block_dest);
-  RI_LAUNCH_CHECK();
-  return RI_OK;
-}
-
-int block_stats(const Plan& p, const uint8_t* mask, double* stats, hipStream_t s);
+int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s);
 
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s) {
-  ItemSource src{p.items, nullptr, nullptr, 0, p.n_items};
+  ItemSource src{p.items, nullptr, 0, p.n_items};
   hipLaunchKernelGGL(k_block_sumsq, dim3(wgs_for(p, p.n_items)), dim3(GT), 0, s, src, y, p.item_part);
   RI_LAUNCH_CHECK();
-  RI_TRY(block_stats(p, nullptr, p.block_tmp, s));
+  RI_TRY(block_stats(p, nullptr, p.block_tmp, nullptr, s));
   hipLaunchKernelGGL(k_take_even, dim3((p.d + 255) / 256), dim3(256), 0, s, p.block_tmp, out, p.d);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
 
-int block_stats(const Plan& p, const uint8_t* mask, double* stats, hipStream_t s) {
-  hipLaunchKernelGGL(k_block_stats, dim3(p.d), dim3(GT), 0, s, mask, p.item_off, p.item_part, stats);
+int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_block_stats, dim3(p.d), dim3(GT), 0, s, mask, p.item_off, p.item_part, stats, out);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
 
-int degrid_apply(const Plan& p, const float2* grid, float2* y, hipStream_t s) {
-  ItemSource src{p.items, p.active_list, p.active_count, 0, 0};
+int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* mask, hipStream_t s) {
+  ItemSource src{p.items, mask, 0, p.n_items};
   const dim3 grid_dim(wgs_for(p, p.n_items));
 #define ARGS src, p.coord, grid, p.K, p.tpa, p.poly, y, (const float2*)nullptr, (const float2*)nullptr, (double*)nullptr
   RI_TILE_DISPATCH(k_degrid, DG_APPLY)
@@ -497,9 +458,9 @@ int degrid_apply(const Plan& p, const float2* grid, float2* y, hipStream_t s) {
 }
 
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
-                    const int* list, const int* count, int base, int count_host, hipStream_t s) {
-  ItemSource src{p.items, list, count, base, count_host};
-  const dim3 grid_dim(wgs_for(p, list ? p.n_items : count_host));
+                    const uint8_t* mask, int base, int count, hipStream_t s) {
+  ItemSource src{p.items, mask, base, count};
+  const dim3 grid_dim(wgs_for(p, count));
 #define ARGS src, p.coord, grid, p.K, p.tpa, p.poly, e, y, v, p.item_part
   RI_TILE_DISPATCH(k_degrid, DG_RESIDUAL)
 #undef ARGS

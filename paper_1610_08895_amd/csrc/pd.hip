@@ -53,15 +53,6 @@ struct ri_pd_s {
 namespace ri {
 namespace {
 
-__global__ void k_export_stats(const uint8_t* __restrict__ mask, const double* __restrict__ in,
-                               double* __restrict__ out, int d) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d; i += gridDim.x * blockDim.x) {
-    const bool act = mask == nullptr || mask[i] != 0;
-    out[2 * i] = act ? in[2 * i] : __builtin_nan("");
-    out[2 * i + 1] = act ? in[2 * i + 1] : __builtin_nan("");
-  }
-}
-
 bool capturing(hipStream_t s) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
@@ -127,14 +118,6 @@ int refresh_sum(ri_pd_s* P, hipStream_t s) {
   const Plan& p = *P->plan;
   RI_TRY(zero_c64(P->sum, size_t(p.K) * p.K, s));
   return grid_all(p, P->v, P->sum, s);
-}
-
-int export_stats(ri_pd_s* P, const uint8_t* mask, double* stats, hipStream_t s) {
-  if (!stats) return RI_OK;
-  hipLaunchKernelGGL(k_export_stats, dim3((P->plan->d + 255) / 256), dim3(256), 0, s, mask, P->stats, stats,
-                     P->plan->d);
-  RI_LAUNCH_CHECK();
-  return RI_OK;
 }
 
 int sparsity_branch(ri_pd_s* P, hipStream_t s) {
@@ -242,17 +225,15 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
     RI_TRY(ri::sparsity_branch(P, stream));
   }
   // data-fidelity branch
-  RI_STAGE(P, RI_STAGE_ACTIVE, stream, ri::build_active(p, mask, stream));
   RI_STAGE(P, RI_STAGE_FFT_ROWS, stream, ri::fft_forward_rows(p, P->xt, stream));
   RI_STAGE(P, RI_STAGE_FFT_COLS, stream, ri::fft_forward_cols(p, p.grid, stream));
   RI_STAGE(P, RI_STAGE_DEGRID, stream,
-           ri::degrid_residual(p, p.grid, P->y, P->v, P->e, p.active_list, p.active_count, 0, 0, stream));
-  RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, mask, P->stats, stream));
+           ri::degrid_residual(p, p.grid, P->y, P->v, P->e, mask, 0, p.n_items, stream));
+  RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, mask, P->stats, stats, stream));
   RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project(p, P->e, P->v, P->stats, P->eps, mask, P->sum, stream));
   RI_STAGE(P, RI_STAGE_GRID_HALO, stream, ri::grid_halo(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows(p, P->g, stream));
-  RI_STAGE(P, RI_STAGE_STATS, stream, ri::export_stats(P, mask, stats, stream));
   // join, then Psi s and the primal update
   if (fork) RI_HIP(hipStreamWaitEvent(stream, P->ev_join, 0));
   RI_TRY(ri::primal_update(P, stream));
@@ -269,17 +250,16 @@ int ri_pd_step_plain(ri_pd P, const uint8_t* mask_host, double* stats, hipStream
     mask_host = ones.data();
   }
   RI_HIP(hipMemcpyAsync(P->mask_dev, mask_host, p.d, hipMemcpyHostToDevice, stream));
-  RI_STAGE(P, RI_STAGE_ACTIVE, stream, ri::build_active(p, P->mask_dev, stream));
   RI_STAGE(P, RI_STAGE_FFT_ROWS, stream, ri::fft_forward_rows(p, P->xt, stream));
   RI_STAGE(P, RI_STAGE_FFT_COLS, stream, ri::fft_forward_cols(p, p.grid, stream));
   RI_TRY(ri::stage_begin(P, RI_STAGE_DEGRID, stream));
   for (int i = 0; i < p.d; ++i) {
     if (!mask_host[i]) continue;
     const int a = p.item_off_host[i], b = p.item_off_host[i + 1];
-    RI_TRY(ri::degrid_residual(p, p.grid, P->y, P->v, P->e, nullptr, nullptr, a, b - a, stream));
+    RI_TRY(ri::degrid_residual(p, p.grid, P->y, P->v, P->e, nullptr, a, b - a, stream));
   }
   RI_TRY(ri::stage_end(P, RI_STAGE_DEGRID, stream));
-  RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, P->mask_dev, P->stats, stream));
+  RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, P->mask_dev, P->stats, stats, stream));
   RI_TRY(ri::stage_begin(P, RI_STAGE_GRID, stream));
   for (int i = 0; i < p.d; ++i) {
     if (!mask_host[i]) continue;
@@ -288,7 +268,6 @@ int ri_pd_step_plain(ri_pd P, const uint8_t* mask_host, double* stats, hipStream
   RI_TRY(ri::stage_end(P, RI_STAGE_GRID, stream));
   RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows(p, P->g, stream));
-  RI_STAGE(P, RI_STAGE_STATS, stream, ri::export_stats(P, P->mask_dev, stats, stream));
   RI_TRY(ri::sparsity_branch(P, stream));
   RI_TRY(ri::primal_update(P, stream));
   P->iter += 1;

@@ -59,16 +59,13 @@ void destroy_plan(Plan& p) {
   dev_free(p.scale);
   dev_free(p.grid);
   dev_free(p.rowbuf);
-  dev_free(p.active_list);
   dev_free(p.tile_items);
   dev_free(p.iota);
   dev_free(p.units);
   dev_free(p.bunits);
   dev_free(p.item_part);
   dev_free(p.block_tmp);
-  dev_free(p.block_dest);
   dev_free(p.halo);
-  dev_free(p.active_count);
   dev_free(p.norm_tmp);
   dev_free(p.dsum);
 }
@@ -215,16 +212,13 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.scale, n));
   RI_TRY(dev_alloc(&p.grid, size_t(K) * K));
   RI_TRY(dev_alloc(&p.rowbuf, size_t(n) * K));
-  RI_TRY(dev_alloc(&p.active_list, items.size()));
   RI_TRY(dev_alloc(&p.tile_items, items.size()));
   RI_TRY(dev_alloc(&p.iota, items.size()));
   RI_TRY(dev_alloc(&p.units, units.size()));
   RI_TRY(dev_alloc(&p.bunits, bunits.size()));
   RI_TRY(dev_alloc(&p.item_part, 2 * items.size()));
   RI_TRY(dev_alloc(&p.block_tmp, 2 * size_t(d)));
-  RI_TRY(dev_alloc(&p.block_dest, size_t(d)));
   RI_TRY(dev_alloc(&p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8)));
-  RI_TRY(dev_alloc(&p.active_count, 1));
   RI_TRY(dev_alloc(&p.norm_tmp, size_t(n) * n));
   RI_TRY(dev_alloc(&p.dsum, SUMSQ_SCRATCH));
   RI_HIP(hipMemcpyAsync(p.coord, coord_sorted.data(), M * sizeof(uint2), hipMemcpyHostToDevice, s));
@@ -246,9 +240,8 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
 }  // namespace
 
 int phi_apply(const Plan& p, const float* x, float* y, const uint8_t* mask, hipStream_t s) {
-  RI_TRY(build_active(p, mask, s));
   RI_TRY(fft_forward(p, x, p.grid, s));
-  return degrid_apply(p, p.grid, reinterpret_cast<float2*>(y), s);
+  return degrid_apply(p, p.grid, reinterpret_cast<float2*>(y), mask, s);
 }
 
 int phi_adj_apply(const Plan& p, const float* y, float* x, const uint8_t* mask, hipStream_t s) {

@@ -54,14 +54,12 @@ struct Plan {
   float* scale = nullptr;     // n: S along one axis, 1 / phi_hat(l / K)
   float2* grid = nullptr;     // K * K work grid
   float2* rowbuf = nullptr;   // n * K half-transformed rows
-  int* active_list = nullptr; // n_items
   int* tile_items = nullptr;    // n_items, grouped by tile (all blocks)
   int* iota = nullptr;          // n_items: 0, 1, 2, ...
-  int4* units = nullptr;        // tiles with items, by colour, densest first; ranges into tile_items
-  int4* bunits = nullptr;       // per block and colour; ranges into iota
+  int4* units = nullptr;        // tiles with items, densest first; ranges into tile_items
+  int4* bunits = nullptr;       // per block; ranges into iota
   double* item_part = nullptr;  // 2 * n_items per-item partial sums of the block norms
   double* block_tmp = nullptr;  // 2 * d
-  int* block_dest = nullptr;    // d: active-list position of each block's first item
   float2* halo = nullptr;       // n_tiles * (tile + 8)^2 halo patches of the gridding
   int* active_count = nullptr;
   float* norm_tmp = nullptr;  // n * n scratch for power iterations
@@ -80,20 +78,20 @@ int fft_adjoint_cols(const Plan& p, const float2* grid, hipStream_t s);
 int fft_adjoint_rows(const Plan& p, float* x, hipStream_t s);
 
 // ---- launchers implemented in gridding.hip ----
-// Active work list of the blocks selected by mask (NULL = all) into p.active_list.
-int build_active(const Plan& p, const uint8_t* mask, hipStream_t s);
-// stats[2i], stats[2i+1] = per-block sums of the degridding partials, active blocks only.
-int block_stats(const Plan& p, const uint8_t* mask, double* stats, hipStream_t s);
+// stats[2i], stats[2i+1] = per-block sums of the degridding partials, active blocks only;
+// copied to out (may be null) with NaN rows for inactive blocks.
+int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s);
 // out[i] = ||y_i||^2 (FP64) for every block.
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s);
-// y = G b for the active items (operator form).
-int degrid_apply(const Plan& p, const float2* grid, float2* y, hipStream_t s);
+// y = G b for the items of active blocks (operator form).
+int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* mask, hipStream_t s);
 // grid += G^dagger y for the active blocks (operator form; grid zeroed by the caller).
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s);
 // PD residual pass: e = G b - y, r = v + e; stats[2i] = ||r_i||^2, stats[2i+1] = ||e_i||^2 for the
 // blocks whose items are processed (per-item partial sums, then a per-block reduction).
+// Items base .. base + count - 1 (those of inactive blocks skipped).
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
-                    const int* list, const int* count, int base, int count_host, hipStream_t s);
+                    const uint8_t* mask, int base, int count, hipStream_t s);
 // PD projection pass: v_new = (v + e) max(0, 1 - eps/||r||); grid += G^dagger (v_new - v); v = v_new,
 // for the active blocks (tile interiors; grid_halo must follow) or for one block (complete).
 int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
