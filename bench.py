@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="grid tile side (0: library default)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also copy a buffer of this many MiB once (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of "
@@ -129,6 +131,13 @@ def main():
     phi_norm, _ = plan.norm(x0, max_it=50, rtol=0.0)
     psi_norm = 3.0
     log(f"setup {time.time() - t0:.1f}s ||Phi|| ~ {phi_norm:.4g}")
+
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
 
     sol = Solver(plan, sara, y_plan, eps, psi_norm, phi_norm)
     ones = np.ones(plan.d, np.uint8)

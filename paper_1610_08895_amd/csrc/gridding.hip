@@ -37,7 +37,7 @@ namespace ri {
 namespace {
 
 constexpr int GT = 256;    // threads per workgroup
-constexpr int GGT = 1024;  // threads per workgroup of the tile gridding (a dense tile fills a CU)
+constexpr int GGT = 256;  // threads per workgroup of the tile gridding
 
 __device__ __forceinline__ void kb_weights(unsigned packed, const KBPoly& P, float* w, int& cell) {
   cell = int(packed >> FRAC_BITS);
@@ -395,7 +395,7 @@ int launch_grid(const Plan& p, const int4* units, int nunits, const int* idx, co
                 const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
                 hipStream_t s, bool with_halo = true) {
   if (nunits > 0) {
-    const int g = p.persistent_wgs > 0 ? p.persistent_wgs : device_cus() * 2;
+    const int g = p.persistent_wgs > 0 ? p.persistent_wgs : device_cus() * 8;
     hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(nunits < g ? nunits : g), dim3(GGT), 0, s, units, nunits, idx,
                        p.items, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, stats, eps);
     RI_LAUNCH_CHECK();
