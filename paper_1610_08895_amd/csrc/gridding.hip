@@ -67,78 +67,97 @@ struct ItemSource {
 
 enum { DG_APPLY = 0, DG_RESIDUAL = 1 };
 
+// LDS row pitch of a staged tile: one more than the region width, so that rows of the
+// tile start in different LDS banks.
+template <int T>
+struct Pitch {
+  static constexpr int TW = T + 8;  // region: the tile plus the kernel's reach
+  static constexpr int TP = T + 9;
+};
+
+// Degridding over units {tile, first, end} of the index list idx (items of one tile,
+// several blocks): the tile and its reach are staged once per unit.
 template <int T, int MODE>
-__global__ __launch_bounds__(GT) void k_degrid(ItemSource src, const uint2* __restrict__ coord,
+__global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, int nunits,
+                                               const int* __restrict__ idx_list, const Item* __restrict__ items,
+                                               const uint8_t* __restrict__ mask, const uint2* __restrict__ coord,
                                                const float2* __restrict__ grid, int K, int tpa, KBPoly P,
                                                float2* __restrict__ out, const float2* __restrict__ y,
                                                const float2* __restrict__ v, double* __restrict__ part) {
-  constexpr int TW = T + 8;
-  __shared__ float2 tile[TW * TW];
+  constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
+  __shared__ float2 tile[TW * TP];
   __shared__ double red[2][GT / 64];
-  for (int a = blockIdx.x; a < src.count; a += gridDim.x) {
-    const int iidx = src.base + a;
-    const Item it = src.items[iidx];
-    if (src.mask != nullptr && src.mask[it.x] == 0) continue;
-    const int ty = it.y / tpa, tx = it.y - (it.y / tpa) * tpa;
+  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+    const int4 un = units[u];
+    bool any = mask == nullptr;
+    for (int q = un.y; q < un.z && !any; ++q) any = mask[items[idx_list[q]].x] != 0;
+    if (!any) continue;
+    const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
     const int gy0 = ty * T - (KB_J / 2 - 1), gx0 = tx * T - (KB_J / 2 - 1);
     for (int idx = threadIdx.x; idx < TW * TW; idx += GT) {
       const int ly = idx / TW, lx = idx - ly * TW;
       const int gy = (gy0 + ly) & (K - 1), gx = (gx0 + lx) & (K - 1);
-      tile[idx] = grid[size_t(gy) * K + gx];
+      tile[ly * TP + lx] = grid[size_t(gy) * K + gx];
     }
     __syncthreads();
-    double sr = 0.0, se = 0.0;
-    const int end = it.z + it.w;
-    for (int m = it.z + threadIdx.x; m < end; m += GT) {
-      const uint2 c = coord[m];
-      float wx[KB_J], wy[KB_J];
-      int cx, cy;
-      kb_weights(c.x, P, wx, cx);
-      kb_weights(c.y, P, wy, cy);
-      const float2* base = &tile[(cy - ty * T) * TW + (cx - tx * T)];
-      float2 acc = make_float2(0.f, 0.f);
+    for (int q = un.y; q < un.z; ++q) {
+      const int iidx = idx_list[q];
+      const Item it = items[iidx];
+      if (mask != nullptr && mask[it.x] == 0) continue;
+      double sr = 0.0, se = 0.0;
+      const int end = it.z + it.w;
+      for (int m = it.z + threadIdx.x; m < end; m += GT) {
+        const uint2 c = coord[m];
+        float wx[KB_J], wy[KB_J];
+        int cx, cy;
+        kb_weights(c.x, P, wx, cx);
+        kb_weights(c.y, P, wy, cy);
+        const float2* base = &tile[(cy - ty * T) * TP + (cx - tx * T)];
+        float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-      for (int ra = 0; ra < KB_J; ++ra) {
-        const float2* row = base + ra * TW;
-        float2 rs = make_float2(0.f, 0.f);
+        for (int ra = 0; ra < KB_J; ++ra) {
+          const float2* row = base + ra * TP;
+          float2 rs = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int b = 0; b < KB_J; ++b) {
-          const float2 g = row[b];
-          rs.x = fmaf(wx[b], g.x, rs.x);
-          rs.y = fmaf(wx[b], g.y, rs.y);
+          for (int b = 0; b < KB_J; ++b) {
+            const float2 g = row[b];
+            rs.x = fmaf(wx[b], g.x, rs.x);
+            rs.y = fmaf(wx[b], g.y, rs.y);
+          }
+          acc.x = fmaf(wy[ra], rs.x, acc.x);
+          acc.y = fmaf(wy[ra], rs.y, acc.y);
         }
-        acc.x = fmaf(wy[ra], rs.x, acc.x);
-        acc.y = fmaf(wy[ra], rs.y, acc.y);
-      }
-      if (MODE == DG_APPLY) {
-        out[m] = acc;
-      } else {
-        const float2 yy = y[m], vv = v[m];
-        const float2 e = make_float2(acc.x - yy.x, acc.y - yy.y);
-        const float2 r = make_float2(vv.x + e.x, vv.y + e.y);
-        out[m] = e;
-        sr += double(r.x) * r.x + double(r.y) * r.y;
-        se += double(e.x) * e.x + double(e.y) * e.y;
-      }
-    }
-    if (MODE == DG_RESIDUAL) {
-      sr = wave_sum(sr);
-      se = wave_sum(se);
-      const int wv = threadIdx.x / 64;
-      if ((threadIdx.x & 63) == 0) {
-        red[0][wv] = sr;
-        red[1][wv] = se;
-      }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < GT / 64; ++k) {
-          a0 += red[0][k];
-          a1 += red[1][k];
+        if (MODE == DG_APPLY) {
+          out[m] = acc;
+        } else {
+          const float2 yy = y[m], vv = v[m];
+          const float2 e = make_float2(acc.x - yy.x, acc.y - yy.y);
+          const float2 r = make_float2(vv.x + e.x, vv.y + e.y);
+          out[m] = e;
+          sr += double(r.x) * r.x + double(r.y) * r.y;
+          se += double(e.x) * e.x + double(e.y) * e.y;
         }
-        part[2 * iidx] = a0;
-        part[2 * iidx + 1] = a1;
+      }
+      if (MODE == DG_RESIDUAL) {
+        sr = wave_sum(sr);
+        se = wave_sum(se);
+        const int wv = threadIdx.x / 64;
+        if ((threadIdx.x & 63) == 0) {
+          red[0][wv] = sr;
+          red[1][wv] = se;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+          for (int k = 0; k < GT / 64; ++k) {
+            a0 += red[0][k];
+            a1 += red[1][k];
+          }
+          part[2 * iidx] = a0;
+          part[2 * iidx + 1] = a1;
+        }
+        __syncthreads();
       }
     }
     __syncthreads();
@@ -208,17 +227,17 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
                                                    int tpa, KBPoly P, const float2* __restrict__ y,
                                                    const float2* __restrict__ e, float2* __restrict__ v,
                                                    const double* __restrict__ stats, const double* __restrict__ eps) {
-  constexpr int TW = T + 8;
+  constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int R0 = KB_J / 2 - 1;  // reach before the tile
-  __shared__ float2 accf[TW * TW];
-  __shared__ unsigned long long acci[TW * TW];
+  __shared__ float2 accf[TW * TP];
+  __shared__ unsigned long long acci[TW * TP];
   __shared__ float2 vals[MAX_BIN];
   __shared__ float red[GGT / 64];
   const int lane = threadIdx.x & 63;
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int4 un = units[u];
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
-    for (int k = threadIdx.x; k < TW * TW; k += GGT) accf[k] = make_float2(0.f, 0.f);
+    for (int k = threadIdx.x; k < TW * TP; k += GGT) accf[k] = make_float2(0.f, 0.f);
     for (int q = un.y; q < un.z; ++q) {
       const Item it = items[idx_list[q]];
       if (mask != nullptr && mask[it.x] == 0) continue;
@@ -245,7 +264,7 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
       }
       for (int off = 32; off > 0; off >>= 1) babs += __shfl_xor(babs, off, 64);
       if (lane == 0) red[threadIdx.x / 64] = babs;
-      for (int k = threadIdx.x; k < TW * TW; k += GGT) acci[k] = 0ull;
+      for (int k = threadIdx.x; k < TW * TP; k += GGT) acci[k] = 0ull;
       __syncthreads();
       float bound = 0.f;
 #pragma unroll
@@ -268,7 +287,7 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
         int cx, cy;
         kb_weights(c.x, P, wx, cx);
         kb_weights(c.y, P, wy, cy);
-        const int b0 = (cy - ty * T) * TW + (cx - tx * T);
+        const int b0 = (cy - ty * T) * TP + (cx - tx * T);
 #pragma unroll
         for (int ra = 0; ra < KB_J; ++ra) {
           const float tr = wy[ra] * val.x * scale, ti = wy[ra] * val.y * scale;
@@ -278,12 +297,12 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
             const unsigned long long w64 =
                 (static_cast<unsigned long long>(static_cast<unsigned>(ii + (ir >> 31))) << 32) |
                 static_cast<unsigned>(ir);
-            atomicAdd(&acci[b0 + ra * TW + b], w64);
+            atomicAdd(&acci[b0 + ra * TP + b], w64);
           }
         }
       }
       __syncthreads();
-      for (int k = threadIdx.x; k < TW * TW; k += GGT) {
+      for (int k = threadIdx.x; k < TW * TP; k += GGT) {
         const unsigned long long w64 = acci[k];
         if (w64) {
           const int ir = static_cast<int>(static_cast<unsigned>(w64));
@@ -299,7 +318,7 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
     float2* patch = halo + size_t(un.x) * TW * TW;
     for (int k = threadIdx.x; k < TW * TW; k += GGT) {
       const int ly = k / TW, lx = k - ly * TW;
-      const float2 a = accf[k];
+      const float2 a = accf[ly * TP + lx];
       const bool inside = ly >= R0 && ly < R0 + T && lx >= R0 && lx < R0 + T;
       if (inside) {
         if (a.x != 0.f || a.y != 0.f) {
@@ -448,9 +467,9 @@ int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, 
 }
 
 int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* mask, hipStream_t s) {
-  ItemSource src{p.items, mask, 0, p.n_items};
-  const dim3 grid_dim(wgs_for(p, p.n_items));
-#define ARGS src, p.coord, grid, p.K, p.tpa, p.poly, y, (const float2*)nullptr, (const float2*)nullptr, (double*)nullptr
+  const dim3 grid_dim(wgs_for(p, p.n_dunits));
+#define ARGS p.dunits, p.n_dunits, p.tile_items, p.items, mask, p.coord, grid, p.K, p.tpa, p.poly, y, \
+             (const float2*)nullptr, (const float2*)nullptr, (double*)nullptr
   RI_TILE_DISPATCH(k_degrid, DG_APPLY)
 #undef ARGS
   RI_LAUNCH_CHECK();
@@ -458,10 +477,22 @@ int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* ma
 }
 
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
-                    const uint8_t* mask, int base, int count, hipStream_t s) {
-  ItemSource src{p.items, mask, base, count};
-  const dim3 grid_dim(wgs_for(p, count));
-#define ARGS src, p.coord, grid, p.K, p.tpa, p.poly, e, y, v, p.item_part
+                    const uint8_t* mask, hipStream_t s) {
+  const dim3 grid_dim(wgs_for(p, p.n_dunits));
+#define ARGS p.dunits, p.n_dunits, p.tile_items, p.items, mask, p.coord, grid, p.K, p.tpa, p.poly, e, y, v, \
+             p.item_part
+  RI_TILE_DISPATCH(k_degrid, DG_RESIDUAL)
+#undef ARGS
+  RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+int degrid_residual_block(const Plan& p, int block, const float2* grid, const float2* y, const float2* v,
+                          float2* e, hipStream_t s) {
+  const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
+  const dim3 grid_dim(wgs_for(p, b - a));
+#define ARGS p.bunits + a, b - a, p.iota, p.items, (const uint8_t*)nullptr, p.coord, grid, p.K, p.tpa, p.poly, e, \
+             y, v, p.item_part
   RI_TILE_DISPATCH(k_degrid, DG_RESIDUAL)
 #undef ARGS
   RI_LAUNCH_CHECK();

@@ -228,7 +228,7 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
   RI_STAGE(P, RI_STAGE_FFT_ROWS, stream, ri::fft_forward_rows(p, P->xt, stream));
   RI_STAGE(P, RI_STAGE_FFT_COLS, stream, ri::fft_forward_cols(p, p.grid, stream));
   RI_STAGE(P, RI_STAGE_DEGRID, stream,
-           ri::degrid_residual(p, p.grid, P->y, P->v, P->e, mask, 0, p.n_items, stream));
+           ri::degrid_residual(p, p.grid, P->y, P->v, P->e, mask, stream));
   RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, mask, P->stats, stats, stream));
   RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project(p, P->e, P->v, P->stats, P->eps, mask, P->sum, stream));
   RI_STAGE(P, RI_STAGE_GRID_HALO, stream, ri::grid_halo(p, P->sum, stream));
@@ -255,8 +255,7 @@ int ri_pd_step_plain(ri_pd P, const uint8_t* mask_host, double* stats, hipStream
   RI_TRY(ri::stage_begin(P, RI_STAGE_DEGRID, stream));
   for (int i = 0; i < p.d; ++i) {
     if (!mask_host[i]) continue;
-    const int a = p.item_off_host[i], b = p.item_off_host[i + 1];
-    RI_TRY(ri::degrid_residual(p, p.grid, P->y, P->v, P->e, nullptr, a, b - a, stream));
+    RI_TRY(ri::degrid_residual_block(p, i, p.grid, P->y, P->v, P->e, stream));
   }
   RI_TRY(ri::stage_end(P, RI_STAGE_DEGRID, stream));
   RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, P->mask_dev, P->stats, stats, stream));

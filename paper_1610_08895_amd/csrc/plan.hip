@@ -63,6 +63,7 @@ void destroy_plan(Plan& p) {
   dev_free(p.iota);
   dev_free(p.units);
   dev_free(p.bunits);
+  dev_free(p.dunits);
   dev_free(p.item_part);
   dev_free(p.block_tmp);
   dev_free(p.halo);
@@ -182,6 +183,22 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
     for (int t : ts) units.push_back(make_int4(t, tile_cnt[t], tile_cnt[t + 1], 0));
   }
   p.n_units = int(units.size());
+  std::vector<int4> dunits;
+  for (const int4& un : units) {
+    int a = un.y, acc = 0;
+    for (int q = un.y; q < un.z; ++q) {
+      const int w = items[tile_items[q]].w;
+      if (q > a && acc + w > DUNIT_VIS) {
+        dunits.push_back(make_int4(un.x, a, q, acc));
+        a = q;
+        acc = 0;
+      }
+      acc += w;
+    }
+    dunits.push_back(make_int4(un.x, a, un.z, acc));
+  }
+  std::stable_sort(dunits.begin(), dunits.end(), [](const int4& l, const int4& r) { return l.w > r.w; });
+  p.n_dunits = int(dunits.size());
   p.bunit_off_host.assign(size_t(d) + 1, 0);
   for (int i = 0; i < d; ++i) {
     p.bunit_off_host[i] = int(bunits.size());
@@ -216,6 +233,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.iota, items.size()));
   RI_TRY(dev_alloc(&p.units, units.size()));
   RI_TRY(dev_alloc(&p.bunits, bunits.size()));
+  RI_TRY(dev_alloc(&p.dunits, dunits.size()));
   RI_TRY(dev_alloc(&p.item_part, 2 * items.size()));
   RI_TRY(dev_alloc(&p.block_tmp, 2 * size_t(d)));
   RI_TRY(dev_alloc(&p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8)));
@@ -230,6 +248,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_HIP(hipMemcpyAsync(p.iota, iota.data(), iota.size() * sizeof(int), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.bunits, bunits.data(), bunits.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.dunits, dunits.data(), dunits.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.scale, sc.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
   // tiles without visibilities keep an all-zero halo patch forever
   RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8), s));

@@ -23,7 +23,8 @@ constexpr unsigned FRAC_MASK = (1u << FRAC_BITS) - 1u;
 // A work item: up to `bin` visibilities of one block that fall in one grid tile.
 // x = block, y = tile (ty * tiles_per_axis + tx), z = first plan position, w = count.
 using Item = int4;
-constexpr int MAX_BIN = 1024;  // largest `bin` (the gridding kernel stages an item's values in LDS)
+constexpr int MAX_BIN = 1024;    // largest `bin` (the gridding kernel stages an item's values in LDS)
+constexpr int DUNIT_VIS = 4096;  // visibilities per degridding unit (several items of one tile)
 
 struct Plan {
   int n = 0, K = 0, J = KB_J, d = 0;
@@ -41,6 +42,7 @@ struct Plan {
   // gridding units {tile, first, end} over an item index list: all blocks together (densest
   // tile first), and block by block
   int n_units = 0;
+  int n_dunits = 0;                 // degridding units: items of one tile, <= DUNIT_VIS visibilities
   std::vector<int> bunit_off_host;  // d + 1
   std::vector<int64_t> order_host;  // plan position -> user index
   std::vector<int64_t> block_off_host;
@@ -58,6 +60,7 @@ struct Plan {
   int* iota = nullptr;          // n_items: 0, 1, 2, ...
   int4* units = nullptr;        // tiles with items, densest first; ranges into tile_items
   int4* bunits = nullptr;       // per block; ranges into iota
+  int4* dunits = nullptr;       // degridding units, densest first; ranges into tile_items
   double* item_part = nullptr;  // 2 * n_items per-item partial sums of the block norms
   double* block_tmp = nullptr;  // 2 * d
   float2* halo = nullptr;       // n_tiles * (tile + 8)^2 halo patches of the gridding
@@ -89,9 +92,11 @@ int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* ma
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s);
 // PD residual pass: e = G b - y, r = v + e; stats[2i] = ||r_i||^2, stats[2i+1] = ||e_i||^2 for the
 // blocks whose items are processed (per-item partial sums, then a per-block reduction).
-// Items base .. base + count - 1 (those of inactive blocks skipped).
+// All items (those of inactive blocks skipped), or the items of one block.
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
-                    const uint8_t* mask, int base, int count, hipStream_t s);
+                    const uint8_t* mask, hipStream_t s);
+int degrid_residual_block(const Plan& p, int block, const float2* grid, const float2* y, const float2* v,
+                          float2* e, hipStream_t s);
 // PD projection pass: v_new = (v + e) max(0, 1 - eps/||r||); grid += G^dagger (v_new - v); v = v_new,
 // for the active blocks (tile interiors; grid_halo must follow) or for one block (complete).
 int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
