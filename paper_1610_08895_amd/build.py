@@ -34,9 +34,15 @@ COMMON = [
 ]
 
 
+# Per-source extra flags.  The gridding kernels round with floor(x + 0.5), which becomes
+# one v_cvt_rpi_i32_f32 only when NaN and infinity need not be honoured; every value they
+# round is finite.
+EXTRA = {"gridding.hip": ["-fno-honor-nans", "-fno-honor-infinities"]}
+
+
 def _compile(src, verbose):
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *COMMON, "-c", src, "-o", obj]
+    cmd = [hipcc(), *COMMON, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -26,10 +26,10 @@
 // read-modify-write (no other workgroup writes it) and stores the reach outside the
 // interior in a per-tile halo patch; a second kernel adds the neighbours' patches into
 // each tile's border cells.  No global atomics are needed, and one launch covers all tiles
-// (densest first).  Inside an item,
-// consecutive lanes take visibilities a stride apart in sorted order, so lanes of one
-// LDS atomic instruction rarely hit the same cell.  Items whose values are all zero (a
-// block whose dual did not change) are skipped.
+// (densest first).  Inside an item consecutive lanes take consecutive visibilities, which
+// the plan orders so that the 64 of one wavefront spread evenly over the LDS banks of the
+// staged tile.  Items whose values are all zero (a block whose dual did not change) are
+// skipped.
 #include "plan.hpp"
 
 namespace ri {
@@ -57,13 +57,15 @@ __device__ __forceinline__ void kb_weights(unsigned packed, const KBPoly& P, flo
   }
 }
 
-// Items base .. base + count - 1, of which those whose block has mask[block] == 0 are
-// skipped (mask may be null).
+// Items base .. base + count - 1.
 struct ItemSource {
   const Item* items;
-  const uint8_t* mask;
   int base, count;
 };
+
+// Rounds to the nearest integer, halves upwards (one v_cvt_rpi_i32_f32: this file is
+// compiled without NaN and infinity semantics, and the values here are finite).
+__device__ __forceinline__ int round_half_up(float x) { return int(floorf(x + 0.5f)); }
 
 enum { DG_APPLY = 0, DG_RESIDUAL = 1 };
 
@@ -172,9 +174,10 @@ __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ 
   __shared__ double red[2][GT / 64];
   const int i = blockIdx.x;
   if (mask != nullptr && mask[i] == 0) {
-    if (out != nullptr && threadIdx.x == 0) {
-      out[2 * i] = __builtin_nan("");
-      out[2 * i + 1] = __builtin_nan("");
+    if (out != nullptr && threadIdx.x == 0) {  // quiet NaN, stored as its bit pattern
+      unsigned long long* o = reinterpret_cast<unsigned long long*>(out);
+      o[2 * i] = 0x7ff8000000000000ull;
+      o[2 * i + 1] = 0x7ff8000000000000ull;
     }
     return;
   }
@@ -207,16 +210,17 @@ __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ 
 
 enum { GR_APPLY = 0, GR_PROJECT = 1 };
 
+
 // A gridding unit: one tile and the range [b, e) of idx[] listing the items that fall in
-// it (x = tile, y = b, z = e).
+// it (x = tile, y = b, z = e, w = their visibility count).
 //
 // Per item the contributions are accumulated exactly in LDS with 64-bit integer atomics
 // (LDS integer atomics are an order of magnitude faster than LDS float atomics on this
 // hardware), Re in the low and Im in the high 32 bits of one word: every value is scaled
 // by a power of two 2^E chosen from the item's sum of |Re| + |Im|, which bounds any cell's
 // sum, so each field stays below 2^30 in magnitude; the low field's sign borrows from the
-// high field exactly, and decoding subtracts the sign-extended low field.  Rounding is at
-// most 2^-E-1 per contribution.  The integer tile is folded into a float tile after each
+// high field exactly, and decoding subtracts the sign-extended low field.  Rounding (to
+// nearest, halves up) is at most 2^-E-1 per contribution.  The integer tile is folded into a float tile after each
 // item.  At the end the tile interior (owned by this workgroup alone) is added to the grid
 // and the reach outside it is stored in the tile's halo patch for k_grid_halo.
 template <int T, int MODE>
@@ -277,12 +281,12 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
       int ex;
       frexpf(bound * 1.0001f, &ex);
       const float scale = ldexpf(1.f, 30 - ex), inv = ldexpf(1.f, ex - 30);
-      const int S = (it.w + 63) >> 6;  // visibilities per lane slot
-      for (int j = threadIdx.x; j < 64 * S; j += GGT) {
-        const int s = lane * S + (j >> 6);
-        if (s >= it.w) continue;
+      // consecutive visibilities go to consecutive lanes (the plan spreads each 64 of
+      // them over the LDS banks)
+      for (int s = threadIdx.x; s < it.w; s += GGT) {
         const uint2 c = coord[it.z + s];
         const float2 val = vals[s];
+        const float vr = val.x * scale, vi = val.y * scale;
         float wx[KB_J], wy[KB_J];
         int cx, cy;
         kb_weights(c.x, P, wx, cx);
@@ -290,10 +294,10 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
         const int b0 = (cy - ty * T) * TP + (cx - tx * T);
 #pragma unroll
         for (int ra = 0; ra < KB_J; ++ra) {
-          const float tr = wy[ra] * val.x * scale, ti = wy[ra] * val.y * scale;
+          const float tr = wy[ra] * vr, ti = wy[ra] * vi;
 #pragma unroll
           for (int b = 0; b < KB_J; ++b) {
-            const int ir = __float2int_rn(wx[b] * tr), ii = __float2int_rn(wx[b] * ti);
+            const int ir = round_half_up(wx[b] * tr), ii = round_half_up(wx[b] * ti);
             const unsigned long long w64 =
                 (static_cast<unsigned long long>(static_cast<unsigned>(ii + (ir >> 31))) << 32) |
                 static_cast<unsigned>(ir);
@@ -451,7 +455,7 @@ int grid_units(const Plan& p, const int4* units, int nunits, const int* idx, con
 int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s);
 
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s) {
-  ItemSource src{p.items, nullptr, 0, p.n_items};
+  ItemSource src{p.items, 0, p.n_items};
   hipLaunchKernelGGL(k_block_sumsq, dim3(wgs_for(p, p.n_items)), dim3(GT), 0, s, src, y, p.item_part);
   RI_LAUNCH_CHECK();
   RI_TRY(block_stats(p, nullptr, p.block_tmp, nullptr, s));

@@ -71,6 +71,25 @@ void destroy_plan(Plan& p) {
   dev_free(p.dsum);
 }
 
+// Reorders the visibilities of one work item (sorted by tile-local cell, key low word =
+// ly * T + lx) so that every 64 consecutive ones, which one wavefront processes together,
+// spread their staged-tile addresses ly * (T + 9) + lx evenly over the LDS banks: the
+// visibilities are dealt round-robin from one queue per bank (32 banks of 8-byte words).
+void lds_bank_order(std::pair<uint64_t, int64_t>* kv, int64_t w, int T) {
+  constexpr int NB = 32;
+  std::vector<std::pair<uint64_t, int64_t>> q[NB];
+  for (int64_t k = 0; k < w; ++k) {
+    const uint32_t local = uint32_t(kv[k].first);
+    const uint32_t ly = local / T, lx = local % T;
+    q[(ly * uint32_t(T + 9) + lx) % NB].push_back(kv[k]);
+  }
+  size_t head[NB] = {};
+  int64_t out = 0;
+  while (out < w)
+    for (int b = 0; b < NB; ++b)
+      if (head[b] < q[b].size()) kv[out++] = q[b][head[b]++];
+}
+
 int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t* off, int J, double beta,
                 const ri_tuning* tune, hipStream_t s) {
   if (!is_pow2(n) || n < 16 || n > 2048) return fail(RI_EINVAL, "n=%d must be a power of two in [16, 2048]", n);
@@ -132,17 +151,20 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
       kv[m - lo] = {(tile << 32) | local, m};
     }
     std::sort(kv.begin(), kv.end());
-    for (int64_t k = 0; k < hi - lo; ++k) p.order_host[lo + k] = kv[k].second;
     auto& its = block_items[i];
     int64_t k = 0;
     while (k < hi - lo) {
       const uint64_t tile = kv[k].first >> 32;
       int64_t e = k;
       while (e < hi - lo && (kv[e].first >> 32) == tile) ++e;
-      for (int64_t a = k; a < e; a += p.bin)
-        its.push_back(make_int4(i, int(tile), int(lo + a), int(std::min<int64_t>(p.bin, e - a))));
+      for (int64_t a = k; a < e; a += p.bin) {
+        const int64_t w = std::min<int64_t>(p.bin, e - a);
+        lds_bank_order(kv.data() + a, w, T);
+        its.push_back(make_int4(i, int(tile), int(lo + a), int(w)));
+      }
       k = e;
     }
+    for (int64_t k = 0; k < hi - lo; ++k) p.order_host[lo + k] = kv[k].second;
   };
   {
     std::vector<std::thread> th;
@@ -180,7 +202,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
     for (int t = 0; t < p.n_tiles; ++t)
       if (tile_vis[t] > 0) ts.push_back(t);
     std::stable_sort(ts.begin(), ts.end(), [&](int a, int b) { return tile_vis[a] > tile_vis[b]; });
-    for (int t : ts) units.push_back(make_int4(t, tile_cnt[t], tile_cnt[t + 1], 0));
+    for (int t : ts) units.push_back(make_int4(t, tile_cnt[t], tile_cnt[t + 1], tile_vis[t]));
   }
   p.n_units = int(units.size());
   std::vector<int4> dunits;
@@ -203,9 +225,9 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   for (int i = 0; i < d; ++i) {
     p.bunit_off_host[i] = int(bunits.size());
     for (int k = p.item_off_host[i]; k < p.item_off_host[i + 1];) {
-      int e = k;
-      while (e < p.item_off_host[i + 1] && items[e].y == items[k].y) ++e;
-      bunits.push_back(make_int4(items[k].y, k, e, 0));
+      int e = k, vis = 0;
+      while (e < p.item_off_host[i + 1] && items[e].y == items[k].y) vis += items[e++].w;
+      bunits.push_back(make_int4(items[k].y, k, e, vis));
       k = e;
     }
   }
