@@ -36,10 +36,10 @@ WORKLOAD = "n1024_m4m_d64"
 # the kernel each timed stage launches in the batched step
 STAGE_KERNEL = {
     "fft_rows": "k_fwd_rows<2048, 1, 256>", "fft_cols": "k_fwd_cols<2048, 8, 512>",
-    "degrid": "k_degrid<32, 1>", "block_norms": "k_block_stats", "grid": "k_grid_tiles<32, 1>",
-    "grid_halo": "k_grid_halo<32>",
+    "degrid": "k_degrid<{T}, 1>", "block_norms": "k_block_stats", "grid": "k_grid_tiles<{T}, 1>",
+    "grid_halo": "k_grid_halo<{T}>",
     "ifft_cols": "k_adj_cols<2048, 8, 512>", "ifft_rows": "k_adj_rows<2048, 1, 256>",
-    "psi_adj": "k_dwt_level (4 launches)", "psi_synth": "k_idwt_level (3 launches)", "update": "k_idwt_top<1>",
+    "psi_adj": "k_dwt_level (4 launches)", "psi_synth": "k_idwt_level (3 launches) + k_idwt_top", "update": "k_primal_update",
 }
 
 
@@ -65,11 +65,12 @@ def stage_bytes(n, M_active, wavelets=8):
         # LL scratch out+in between levels
         "psi_adj": 4 * N + 8 * N + nw * 8 * (3 * N // 4 + 3 * N // 16 + 3 * N // 64 + 4 * N // 256)
                    + nw * 4 * 2 * (N // 4 + N // 16 + N // 64),
-        # Psi s below the finest level: coefficients of levels 2.. in, LL scratch out
+        # Psi s: coefficients of levels 2.. in, LL scratch out and in between levels, then the
+        # finest level (LL1 scratch, level-1 details, Dirac in; s~ out)
         "psi_synth": nw * 4 * (3 * N // 16 + 3 * N // 64 + 4 * N // 256) + nw * 4 * 2 * (N // 16 + N // 64)
-                     + nw * 4 * (N // 4),
-        # finest level + update: LL1 scratch, level-1 details, Dirac, g, x in; x, x~ out
-        "update": nw * 4 * (N // 4 + 3 * N // 4) + 4 * N * 3 + 4 * N * 2,
+                     + nw * 4 * (N // 4) + nw * 4 * (N // 4 + 3 * N // 4) + 4 * N + 4 * N,
+        # steps 17-18: s~, g, x in; x, x~ out
+        "update": 4 * N * 3 + 4 * N * 2,
     }
 
 
@@ -254,7 +255,7 @@ def main():
         "stage_algorithmic_bytes": sb,
         "snr_db": round(snr_db, 3),
         "stage_ms_per_launch": {k: round(v, 5) for k, v in mean_ms.items()},
-        "roofline": {"kernel": dom, "kernel_symbol": STAGE_KERNEL.get(dom, dom), "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": dom, "kernel_symbol": STAGE_KERNEL.get(dom, dom).format(T=args.tile or 32), "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes": alg},
         "cpu_baseline": cpu,

@@ -197,8 +197,8 @@ enum {
   RI_STAGE_IFFT_COLS = 6,   /* Z^dagger F^dagger, column pass (step 17)                     */
   RI_STAGE_IFFT_ROWS = 7,   /* Z^dagger F^dagger, row pass (step 17)                        */
   RI_STAGE_PSI_ADJ = 8,     /* Psi^dagger x~ and dual clip, all levels (step 13)            */
-  RI_STAGE_PSI_SYNTH = 9,   /* Psi s, every level but the finest (step 14)                  */
-  RI_STAGE_UPDATE = 10,     /* finest level of Psi s + steps 17-18                         */
+  RI_STAGE_PSI_SYNTH = 9,   /* s~ = Psi s, all levels (step 14)                             */
+  RI_STAGE_UPDATE = 10,     /* steps 17-18, elementwise                                     */
   RI_STAGE_COUNT = 11
 };
 

@@ -5,14 +5,15 @@
 // G_i^dagger v_i is added to the running sum sum_i M_i^dagger v~_i, which therefore holds
 // the latest v~_i of active blocks and the kept v~_i of inactive ones (step 11); then
 // g = Re Z^dagger F^dagger (that sum).
-// Sparsity branch (steps 13-14): s <- clip(s + Psi^dagger x~, -alpha, alpha), then the
-// synthesis levels of Psi s below the finest.
+// Sparsity branch (steps 13-14): s <- clip(s + Psi^dagger x~, -alpha, alpha), then
+// s~ = Psi s.
 // The two branches depend only on x~ of the previous iteration (the paper runs them
 // concurrently); the batched step forks the sparsity branch onto a side stream and joins
-// before the last kernel, which finishes Psi s and applies steps 17-18.
+// before the last kernel, the elementwise steps 17-18.
 //
 // The running sum is kept in FP32 and updated by differences; ri_pd_refresh (and setting
 // V) rebuilds it from the stored v, bounding accumulated rounding.
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
@@ -31,6 +32,7 @@ struct ri_pd_s {
   float* x = nullptr;
   float* xt = nullptr;
   float* s = nullptr;
+  float* st = nullptr;     // s~ = Psi s
   float* g = nullptr;
   float2* sum = nullptr;   // sum_i M_i^dagger v~_i on the K x K grid
   double* eps = nullptr;   // d
@@ -99,6 +101,7 @@ void destroy_pd(ri_pd_s* P) {
   dev_free(P->x);
   dev_free(P->xt);
   dev_free(P->s);
+  dev_free(P->st);
   dev_free(P->g);
   dev_free(P->sum);
   dev_free(P->eps);
@@ -121,15 +124,41 @@ int refresh_sum(ri_pd_s* P, hipStream_t s) {
 }
 
 int sparsity_branch(ri_pd_s* P, hipStream_t s) {
-  // step 13 (Moreau form of the soft-threshold), then Psi s below the finest level
+  // step 13 (Moreau form of the soft-threshold), then step 14
   RI_STAGE(P, RI_STAGE_PSI_ADJ, s, psi_adj_apply(*P->sara, P->xt, P->s, true, P->alpha, s));
-  RI_STAGE(P, RI_STAGE_PSI_SYNTH, s, psi_synth_lower(*P->sara, P->s, s));
+  RI_STAGE(P, RI_STAGE_PSI_SYNTH, s, psi_apply(*P->sara, P->s, P->st, s));
+  return RI_OK;
+}
+
+// Steps 17-18: x <- max(0, x - tau (sigma s~ + varsigma g)), x~ = 2 x_new - x_old.
+__global__ __launch_bounds__(256) void k_primal_update(const float4* __restrict__ st, const float4* __restrict__ g,
+                                                       float4* __restrict__ x, float4* __restrict__ xt, int n4,
+                                                       float tau, float sigma, float varsigma) {
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < n4; k += gridDim.x * 256) {
+    const float4 a = st[k], b = g[k], xo = x[k];
+    float4 xn;
+    xn.x = fmaxf(0.f, xo.x - tau * (sigma * a.x + varsigma * b.x));
+    xn.y = fmaxf(0.f, xo.y - tau * (sigma * a.y + varsigma * b.y));
+    xn.z = fmaxf(0.f, xo.z - tau * (sigma * a.z + varsigma * b.z));
+    xn.w = fmaxf(0.f, xo.w - tau * (sigma * a.w + varsigma * b.w));
+    x[k] = xn;
+    xt[k] = make_float4(2.f * xn.x - xo.x, 2.f * xn.y - xo.y, 2.f * xn.z - xo.z, 2.f * xn.w - xo.w);
+  }
+}
+
+int primal_update_launch(ri_pd_s* P, hipStream_t s) {
+  const int n4 = P->plan->n * P->plan->n / 4;  // n >= 16
+  const int blocks = std::min((n4 + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_primal_update, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const float4*>(P->st),
+                     reinterpret_cast<const float4*>(P->g), reinterpret_cast<float4*>(P->x),
+                     reinterpret_cast<float4*>(P->xt), n4, float(P->prm.tau), float(P->prm.sigma),
+                     float(P->prm.varsigma));
+  RI_LAUNCH_CHECK();
   return RI_OK;
 }
 
 int primal_update(ri_pd_s* P, hipStream_t s) {
-  PrimalUpdate u{P->g, P->x, P->xt, float(P->prm.tau), float(P->prm.sigma), float(P->prm.varsigma)};
-  RI_STAGE(P, RI_STAGE_UPDATE, s, psi_top_update(*P->sara, P->s, u, s));
+  RI_STAGE(P, RI_STAGE_UPDATE, s, primal_update_launch(P, s));
   return RI_OK;
 }
 
@@ -172,6 +201,7 @@ int ri_pd_create(ri_pd* out, ri_plan plan, ri_sara sara, const float* y, const d
   step(ri::dev_alloc(&P->x, N));
   step(ri::dev_alloc(&P->xt, N));
   step(ri::dev_alloc(&P->s, size_t(S.b) * N));
+  step(ri::dev_alloc(&P->st, N));
   step(ri::dev_alloc(&P->g, N));
   step(ri::dev_alloc(&P->sum, KK));
   step(ri::dev_alloc(&P->eps, size_t(p.d)));
@@ -192,6 +222,7 @@ int ri_pd_create(ri_pd* out, ri_plan plan, ri_sara sara, const float* y, const d
   step(rc == RI_OK ? ri::zero_f32(P->x, N, stream) : rc);
   step(rc == RI_OK ? ri::zero_f32(P->xt, N, stream) : rc);
   step(rc == RI_OK ? ri::zero_f32(P->s, size_t(S.b) * N, stream) : rc);
+  step(rc == RI_OK ? ri::zero_f32(P->st, N, stream) : rc);
   step(rc == RI_OK ? ri::zero_f32(P->g, N, stream) : rc);
   step(rc == RI_OK ? ri::zero_c64(P->sum, KK, stream) : rc);
   if (rc == RI_OK && hipStreamSynchronize(stream) != hipSuccess) rc = fail(RI_EHIP, "stream sync failed");
@@ -234,7 +265,7 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
   RI_STAGE(P, RI_STAGE_GRID_HALO, stream, ri::grid_halo(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows(p, P->g, stream));
-  // join, then Psi s and the primal update
+  // join, then the primal update
   if (fork) RI_HIP(hipStreamWaitEvent(stream, P->ev_join, 0));
   RI_TRY(ri::primal_update(P, stream));
   P->iter += 1;

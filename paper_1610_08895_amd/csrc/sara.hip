@@ -129,11 +129,7 @@ struct IdwtArgs {
   float* tmp;
   size_t tmp_stride, ll_off, out_off;
   int n, m, level, levels, dirac, nw;
-  // top level only
-  float* x;
-  const float* g;
-  float* xt;
-  float tau, sigma, varsigma;
+  float* x;  // top level only: the image Psi s
 };
 
 constexpr int RS = TS / 2 + MAX_TAPS / 2;  // LDS stride of a staged subband region
@@ -215,7 +211,6 @@ __global__ __launch_bounds__(ST) void k_idwt_level(IdwtArgs A, const float* __re
 #undef RI_SYNTH
 }
 
-template <int MODE>
 __global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, const float* __restrict__ filt,
                                                  const int* __restrict__ flen) {
   constexpr int PER = TS * TS / 2 / ST;  // output pairs per thread
@@ -243,15 +238,7 @@ __global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, const float* __rest
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const size_t o = size_t(p) * n + q + r;
-      const float st = (r ? acc_o[k] : acc_e[k]) + (A.dirac ? A.s[o] : 0.f);
-      if (MODE == 0) {
-        A.x[o] = st;
-      } else {
-        const float xo = A.x[o];
-        const float xn = fmaxf(0.f, xo - A.tau * (A.sigma * st + A.varsigma * A.g[o]));
-        A.x[o] = xn;
-        A.xt[o] = 2.f * xn - xo;
-      }
+      A.x[o] = (r ? acc_o[k] : acc_e[k]) + (A.dirac ? A.s[o] : 0.f);
     }
   }
 }
@@ -276,7 +263,7 @@ int synthesis_lower(const Sara& S, const float* s, hipStream_t st) {
   for (int lev = S.levels; lev >= 2; --lev) {
     const int m = S.n >> (lev - 1);
     IdwtArgs A{s, S.tmp, S.tmp_stride, lev < S.levels ? S.tmp_off[lev] : 0, S.tmp_off[lev - 1], S.n, m, lev,
-               S.levels, S.dirac, S.nw, nullptr, nullptr, nullptr, 0.f, 0.f, 0.f};
+               S.levels, S.dirac, S.nw, nullptr};
     if (S.nw == 0) break;
     hipLaunchKernelGGL(k_idwt_level, dim3(tiles(m, TS), tiles(m, TS), S.nw), dim3(ST), 0, st, A, S.dfilt,
                        S.dlen);
@@ -285,13 +272,10 @@ int synthesis_lower(const Sara& S, const float* s, hipStream_t st) {
   return RI_OK;
 }
 
-int synthesis_top(const Sara& S, const float* s, const PrimalUpdate* u, float* x, hipStream_t st) {
-  IdwtArgs A{s, S.tmp, S.tmp_stride, S.levels > 1 ? S.tmp_off[1] : 0, 0, S.n, S.n, 1, S.levels, S.dirac, S.nw,
-             u ? u->x : x, u ? u->g : nullptr, u ? u->xt : nullptr, u ? u->tau : 0.f, u ? u->sigma : 0.f,
-             u ? u->varsigma : 0.f};
+int synthesis_top(const Sara& S, const float* s, float* x, hipStream_t st) {
+  IdwtArgs A{s, S.tmp, S.tmp_stride, S.levels > 1 ? S.tmp_off[1] : 0, 0, S.n, S.n, 1, S.levels, S.dirac, S.nw, x};
   const dim3 g(tiles(S.n, TS), tiles(S.n, TS));
-  if (u) hipLaunchKernelGGL(k_idwt_top<1>, g, dim3(ST), 0, st, A, S.dfilt, S.dlen);
-  else hipLaunchKernelGGL(k_idwt_top<0>, g, dim3(ST), 0, st, A, S.dfilt, S.dlen);
+  hipLaunchKernelGGL(k_idwt_top, g, dim3(ST), 0, st, A, S.dfilt, S.dlen);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
@@ -361,13 +345,7 @@ int psi_adj_apply(const Sara& S, const float* x, float* s, bool clip, float alph
 
 int psi_apply(const Sara& S, const float* s, float* x, hipStream_t st) {
   RI_TRY(synthesis_lower(S, s, st));
-  return synthesis_top(S, s, nullptr, x, st);
-}
-
-int psi_synth_lower(const Sara& S, const float* s, hipStream_t st) { return synthesis_lower(S, s, st); }
-
-int psi_top_update(const Sara& S, const float* s, const PrimalUpdate& u, hipStream_t st) {
-  return synthesis_top(S, s, &u, nullptr, st);
+  return synthesis_top(S, s, x, st);
 }
 
 }  // namespace ri

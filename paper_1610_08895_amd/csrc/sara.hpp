@@ -34,21 +34,10 @@ struct Sara {
   double* dsum = nullptr;
 };
 
-struct PrimalUpdate {
-  const float* g;  // Re Z^dagger F^dagger sum_i M_i^dagger v~_i
-  float* x;        // in: x^(t-1), out: x^(t)
-  float* xt;       // out: 2 x^(t) - x^(t-1)
-  float tau, sigma, varsigma;
-};
-
 // s = Psi^dagger x, or with clip: s = clip(s + Psi^dagger x, -alpha, alpha) (step 13 Moreau form).
 int psi_adj_apply(const Sara& S, const float* x, float* s, bool clip, float alpha, hipStream_t st);
 // x = Psi s.
 int psi_apply(const Sara& S, const float* s, float* x, hipStream_t st);
-// Psi s, part 1: synthesis of every level but the finest (into the dictionary's scratch).
-int psi_synth_lower(const Sara& S, const float* s, hipStream_t st);
-// Psi s, part 2, fused with steps 17-18: the finest level summed over all bases,
-// x = max(0, x - tau (sigma Psi s + varsigma g)), xt = 2 x_new - x_old.
-int psi_top_update(const Sara& S, const float* s, const PrimalUpdate& u, hipStream_t st);
+
 
 }  // namespace ri
