@@ -210,7 +210,6 @@ __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ 
 
 enum { GR_APPLY = 0, GR_PROJECT = 1 };
 
-
 // A gridding unit: one tile and the range [b, e) of idx[] listing the items that fall in
 // it (x = tile, y = b, z = e, w = their visibility count).
 //
@@ -220,9 +219,14 @@ enum { GR_APPLY = 0, GR_PROJECT = 1 };
 // by a power of two 2^E chosen from the item's sum of |Re| + |Im|, which bounds any cell's
 // sum, so each field stays below 2^30 in magnitude; the low field's sign borrows from the
 // high field exactly, and decoding subtracts the sign-extended low field.  Rounding (to
-// nearest, halves up) is at most 2^-E-1 per contribution.  The integer tile is folded into a float tile after each
-// item.  At the end the tile interior (owned by this workgroup alone) is added to the grid
-// and the reach outside it is stored in the tile's halo patch for k_grid_halo.
+// nearest, halves up) is at most 2^-E-1 per contribution.  After each item the cells of
+// its footprint's bounding box are folded into a float tile and cleared.  At the end the
+// tile interior (owned by this workgroup alone) is added to the grid and the reach outside
+// it is stored in the tile's halo patch for k_grid_halo.
+//
+// Each thread keeps the values and coordinates of its (at most MAX_BIN / GGT) visibilities
+// of the current item in registers, and loads those of the next active item while the
+// current one is accumulated, so two barriers per item separate the phases.
 template <int T, int MODE>
 __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ units, int nunits,
                                                    const int* __restrict__ idx_list, const Item* __restrict__ items,
@@ -233,92 +237,163 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
                                                    const double* __restrict__ stats, const double* __restrict__ eps) {
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int R0 = KB_J / 2 - 1;  // reach before the tile
+  constexpr int NV = MAX_BIN / GGT;
+  constexpr int NWV = GGT / 64;
   __shared__ float2 accf[TW * TP];
   __shared__ unsigned long long acci[TW * TP];
-  __shared__ float2 vals[MAX_BIN];
-  __shared__ float red[GGT / 64];
-  const int lane = threadIdx.x & 63;
+  __shared__ float red_b[NWV];
+  __shared__ int red_box[4][NWV];  // -row min, row max, -column min, column max
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+
+  auto next_active = [&](int q, int end) {
+    while (q < end && mask != nullptr && mask[items[idx_list[q]].x] == 0) ++q;
+    return q;
+  };
+  // operands of the current item, and the raw loads of the next one
+  float2 val[NV], ra[NV], rb[NV];
+  uint2 crd[NV], rc[NV];
+  auto load_raw = [&](const Item& it) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int s = threadIdx.x + k * GGT;
+      if (s < it.w) {
+        const int m = it.z + s;
+        rc[k] = coord[m];
+        if (MODE == GR_APPLY) {
+          ra[k] = y[m];
+        } else {
+          ra[k] = v[m];
+          rb[k] = e[m];
+        }
+      }
+    }
+  };
+  // values (with the dual update of step 8), the bound and the footprint box, into red_*
+  auto finish = [&](const Item& it, int ty, int tx) {
+    float shrink = 0.f;
+    if (MODE == GR_PROJECT) {
+      const double nr2 = stats[2 * it.x], ep = eps[it.x];
+      shrink = nr2 > ep * ep ? float(1.0 - ep / sqrt(nr2)) : 0.f;
+    }
+    float babs = 0.f;
+    int box[4] = {-TW, -1, -TW, -1};
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int s = threadIdx.x + k * GGT;
+      if (s < it.w) {
+        const int m = it.z + s;
+        if (MODE == GR_APPLY) {
+          val[k] = ra[k];
+        } else {
+          const float2 vn = make_float2((ra[k].x + rb[k].x) * shrink, (ra[k].y + rb[k].y) * shrink);
+          v[m] = vn;
+          val[k] = make_float2(vn.x - ra[k].x, vn.y - ra[k].y);
+        }
+        crd[k] = rc[k];
+        babs += fabsf(val[k].x) + fabsf(val[k].y);
+        const int ly = int(rc[k].y >> FRAC_BITS) - ty * T, lx = int(rc[k].x >> FRAC_BITS) - tx * T;
+        box[0] = max(box[0], -ly);
+        box[1] = max(box[1], ly);
+        box[2] = max(box[2], -lx);
+        box[3] = max(box[3], lx);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      babs += __shfl_xor(babs, off, 64);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) box[j] = max(box[j], __shfl_xor(box[j], off, 64));
+    }
+    if (lane == 0) {
+      red_b[wv] = babs;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) red_box[j][wv] = box[j];
+    }
+  };
+
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int4 un = units[u];
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
-    for (int k = threadIdx.x; k < TW * TP; k += GGT) accf[k] = make_float2(0.f, 0.f);
-    for (int q = un.y; q < un.z; ++q) {
-      const Item it = items[idx_list[q]];
-      if (mask != nullptr && mask[it.x] == 0) continue;
-      float shrink = 0.f;
-      if (MODE == GR_PROJECT) {
-        const double nr2 = stats[2 * it.x], ep = eps[it.x];
-        shrink = nr2 > ep * ep ? float(1.0 - ep / sqrt(nr2)) : 0.f;
-      }
-      // values (and the dual update of step 8), and the bound sum |Re| + |Im|
-      float babs = 0.f;
-      for (int s = threadIdx.x; s < it.w; s += GGT) {
-        const int m = it.z + s;
-        float2 val;
-        if (MODE == GR_APPLY) {
-          val = y[m];
-        } else {
-          const float2 vo = v[m], ee = e[m];
-          const float2 vn = make_float2((vo.x + ee.x) * shrink, (vo.y + ee.y) * shrink);
-          v[m] = vn;
-          val = make_float2(vn.x - vo.x, vn.y - vo.y);
-        }
-        vals[s] = val;
-        babs += fabsf(val.x) + fabsf(val.y);
-      }
-      for (int off = 32; off > 0; off >>= 1) babs += __shfl_xor(babs, off, 64);
-      if (lane == 0) red[threadIdx.x / 64] = babs;
-      for (int k = threadIdx.x; k < TW * TP; k += GGT) acci[k] = 0ull;
-      __syncthreads();
+    for (int k = threadIdx.x; k < TW * TP; k += GGT) {
+      accf[k] = make_float2(0.f, 0.f);
+      acci[k] = 0ull;
+    }
+    int q = next_active(un.y, un.z);
+    Item it = make_int4(0, 0, 0, 0);
+    if (q < un.z) {
+      it = items[idx_list[q]];
+      load_raw(it);
+      finish(it, ty, tx);
+    }
+    __syncthreads();
+    while (q < un.z) {
       float bound = 0.f;
+      int box[4] = {-TW, -1, -TW, -1};
 #pragma unroll
-      for (int k = 0; k < GGT / 64; ++k) bound += red[k];
-      if (bound == 0.f) {  // the item changes nothing
-        __syncthreads();
-        continue;
+      for (int w = 0; w < NWV; ++w) {
+        bound += red_b[w];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) box[j] = max(box[j], red_box[j][w]);
+      }
+      const int qn = next_active(q + 1, un.z);
+      Item itn = make_int4(0, 0, 0, 0);
+      if (qn < un.z) {
+        itn = items[idx_list[qn]];
+        load_raw(itn);
       }
       // 2^E with bound * 2^E <= 2^30 (bound * 1.0001 guards the bound's own rounding)
-      int ex;
-      frexpf(bound * 1.0001f, &ex);
+      int ex = 0;
+      if (bound > 0.f) frexpf(bound * 1.0001f, &ex);
       const float scale = ldexpf(1.f, 30 - ex), inv = ldexpf(1.f, ex - 30);
-      // consecutive visibilities go to consecutive lanes (the plan spreads each 64 of
-      // them over the LDS banks)
-      for (int s = threadIdx.x; s < it.w; s += GGT) {
-        const uint2 c = coord[it.z + s];
-        const float2 val = vals[s];
-        const float vr = val.x * scale, vi = val.y * scale;
-        float wx[KB_J], wy[KB_J];
-        int cx, cy;
-        kb_weights(c.x, P, wx, cx);
-        kb_weights(c.y, P, wy, cy);
-        const int b0 = (cy - ty * T) * TP + (cx - tx * T);
+      if (bound > 0.f) {
 #pragma unroll
-        for (int ra = 0; ra < KB_J; ++ra) {
-          const float tr = wy[ra] * vr, ti = wy[ra] * vi;
+        for (int k = 0; k < NV; ++k) {
+          const int s = threadIdx.x + k * GGT;
+          if (s < it.w) {
+            const float vr = val[k].x * scale, vi = val[k].y * scale;
+            float wx[KB_J], wy[KB_J];
+            int cx, cy;
+            kb_weights(crd[k].x, P, wx, cx);
+            kb_weights(crd[k].y, P, wy, cy);
+            const int b0 = (cy - ty * T) * TP + (cx - tx * T);
 #pragma unroll
-          for (int b = 0; b < KB_J; ++b) {
-            const int ir = round_half_up(wx[b] * tr), ii = round_half_up(wx[b] * ti);
-            const unsigned long long w64 =
-                (static_cast<unsigned long long>(static_cast<unsigned>(ii + (ir >> 31))) << 32) |
-                static_cast<unsigned>(ir);
-            atomicAdd(&acci[b0 + ra * TP + b], w64);
+            for (int r = 0; r < KB_J; ++r) {
+              const float tr = wy[r] * vr, ti = wy[r] * vi;
+#pragma unroll
+              for (int b = 0; b < KB_J; ++b) {
+                const int ir = round_half_up(wx[b] * tr), ii = round_half_up(wx[b] * ti);
+                const unsigned long long w64 =
+                    (static_cast<unsigned long long>(static_cast<unsigned>(ii + (ir >> 31))) << 32) |
+                    static_cast<unsigned>(ir);
+                atomicAdd(&acci[b0 + r * TP + b], w64);
+              }
+            }
           }
         }
       }
       __syncthreads();
-      for (int k = threadIdx.x; k < TW * TP; k += GGT) {
-        const unsigned long long w64 = acci[k];
-        if (w64) {
-          const int ir = static_cast<int>(static_cast<unsigned>(w64));
-          const int ii = static_cast<int>(static_cast<unsigned>((w64 - static_cast<unsigned long long>(
-                                                                          static_cast<long long>(ir))) >> 32));
-          const float2 a = accf[k];
-          accf[k] = make_float2(a.x + float(ir) * inv, a.y + float(ii) * inv);
+      if (bound > 0.f) {
+        // fold and clear the footprint box: rows -box[0] .. box[1] + J - 1, same for columns
+        const int r0 = -box[0], c0 = -box[2];
+        const int nr = box[1] + KB_J - r0, nc = box[3] + KB_J - c0;
+        for (int k = threadIdx.x; k < nr * nc; k += GGT) {
+          const int rr = k / nc;
+          const int idx = (r0 + rr) * TP + c0 + (k - rr * nc);
+          const unsigned long long w64 = acci[idx];
+          if (w64) {
+            acci[idx] = 0ull;
+            const int ir = static_cast<int>(static_cast<unsigned>(w64));
+            const int ii = static_cast<int>(static_cast<unsigned>((w64 - static_cast<unsigned long long>(
+                                                                            static_cast<long long>(ir))) >> 32));
+            const float2 a = accf[idx];
+            accf[idx] = make_float2(a.x + float(ir) * inv, a.y + float(ii) * inv);
+          }
         }
       }
+      if (qn < un.z) finish(itn, ty, tx);
       __syncthreads();
+      q = qn;
+      it = itn;
     }
-    __syncthreads();
     float2* patch = halo + size_t(un.x) * TW * TW;
     for (int k = threadIdx.x; k < TW * TW; k += GGT) {
       const int ly = k / TW, lx = k - ly * TW;
