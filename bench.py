@@ -96,6 +96,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="grid tile side (0: library default)")
+    ap.add_argument("--bin", type=int, default=0, help="max visibilities per work item (0: library default)")
+    ap.add_argument("--slice-vis", type=int, default=0,
+                    help="max visibilities per gridding workgroup of one tile (0: default, -1: no split)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also copy a buffer of this many MiB once (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -118,7 +121,7 @@ def main():
     t0 = time.time()
     inp = synth.make_inputs(w)
     log(f"inputs {time.time() - t0:.1f}s")
-    plan = R.Plan(w.n, inp.uv, inp.block_off, tile=args.tile)
+    plan = R.Plan(w.n, inp.uv, inp.block_off, tile=args.tile, bin=args.bin, slice_vis=args.slice_vis)
     order = plan.order()
     log(f"plan {time.time() - t0:.1f}s items={plan.n_items}")
     x_true = torch.tensor(inp.x_true, dtype=torch.float32, device="cuda")

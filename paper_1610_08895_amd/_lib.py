@@ -22,7 +22,8 @@ P = ctypes.POINTER
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("tile", c_int), ("bin", c_int), ("fft_panel", c_int), ("persistent_wgs", c_int)]
+    _fields_ = [("tile", c_int), ("bin", c_int), ("fft_panel", c_int), ("persistent_wgs", c_int),
+                ("slice_vis", c_int)]
 
 
 class PDParams(ctypes.Structure):

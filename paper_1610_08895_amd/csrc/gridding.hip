@@ -219,14 +219,17 @@ enum { GR_APPLY = 0, GR_PROJECT = 1 };
 // by a power of two 2^E chosen from the item's sum of |Re| + |Im|, which bounds any cell's
 // sum, so each field stays below 2^30 in magnitude; the low field's sign borrows from the
 // high field exactly, and decoding subtracts the sign-extended low field.  Rounding (to
-// nearest, halves up) is at most 2^-E-1 per contribution.  After each item the cells of
-// its footprint's bounding box are folded into a float tile and cleared.  At the end the
-// tile interior (owned by this workgroup alone) is added to the grid and the reach outside
-// it is stored in the tile's halo patch for k_grid_halo.
+// nearest, halves up) is at most 2^-E-1 per contribution.
 //
-// Each thread keeps the values and coordinates of its (at most MAX_BIN / GGT) visibilities
-// of the current item in registers, and loads those of the next active item while the
-// current one is accumulated, so two barriers per item separate the phases.
+// Two integer tiles alternate between items: while item q is accumulated into one, the
+// cells of item q-1's footprint box are folded out of the other (and cleared) into FP32
+// accumulators held in registers, each thread owning fixed cells of the region.  Each
+// thread also keeps the values and coordinates of its (at most MAX_BIN / GGT) visibilities
+// of the current item in registers and loads those of the next active item meanwhile, so
+// one barrier per item separates the phases.  At the end the tile interior (owned by this
+// workgroup alone) is added to the grid and the reach outside it is stored in the tile's
+// halo patch for k_grid_halo (a further slice of a split tile stores its whole region in
+// its slice patch instead).
 template <int T, int MODE>
 __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ units, int nunits,
                                                    const int* __restrict__ idx_list, const Item* __restrict__ items,
@@ -234,15 +237,16 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
                                                    float2* __restrict__ grid, float2* __restrict__ halo, int K,
                                                    int tpa, KBPoly P, const float2* __restrict__ y,
                                                    const float2* __restrict__ e, float2* __restrict__ v,
-                                                   const double* __restrict__ stats, const double* __restrict__ eps) {
+                                                   const double* __restrict__ stats, const double* __restrict__ eps,
+                                                   const int* __restrict__ unit_patch, float2* __restrict__ spatch) {
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int R0 = KB_J / 2 - 1;  // reach before the tile
   constexpr int NV = MAX_BIN / GGT;
   constexpr int NWV = GGT / 64;
-  __shared__ float2 accf[TW * TP];
-  __shared__ unsigned long long acci[TW * TP];
-  __shared__ float red_b[NWV];
-  __shared__ int red_box[4][NWV];  // -row min, row max, -column min, column max
+  constexpr int NC = (TW * TW + GGT - 1) / GGT;  // region cells per thread
+  __shared__ unsigned long long acci[2][TW * TP];
+  __shared__ float red_b[2][NWV];
+  __shared__ int red_box[2][4][NWV];  // -row min, row max, -column min, column max
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
   auto next_active = [&](int q, int end) {
@@ -268,8 +272,8 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
       }
     }
   };
-  // values (with the dual update of step 8), the bound and the footprint box, into red_*
-  auto finish = [&](const Item& it, int ty, int tx) {
+  // values (with the dual update of step 8), the bound and the footprint box into red_*[rb]
+  auto finish = [&](const Item& it, int ty, int tx, int buf) {
     float shrink = 0.f;
     if (MODE == GR_PROJECT) {
       const double nr2 = stats[2 * it.x], ep = eps[it.x];
@@ -304,35 +308,59 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
       for (int j = 0; j < 4; ++j) box[j] = max(box[j], __shfl_xor(box[j], off, 64));
     }
     if (lane == 0) {
-      red_b[wv] = babs;
+      red_b[buf][wv] = babs;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) red_box[j][wv] = box[j];
+      for (int j = 0; j < 4; ++j) red_box[buf][j][wv] = box[j];
+    }
+  };
+  // this thread's region cells
+  float2 acc[NC];
+  auto fold = [&](int buf, const int* box, float inv) {
+    const int r0 = -box[0], r1 = box[1] + KB_J, c0 = -box[2], c1 = box[3] + KB_J;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c = threadIdx.x + j * GGT;
+      const int ly = c / TW, lx = c - (c / TW) * TW;
+      if (c < TW * TW && ly >= r0 && ly < r1 && lx >= c0 && lx < c1) {
+        unsigned long long* cell = &acci[buf][ly * TP + lx];
+        const unsigned long long w64 = *cell;
+        if (w64) {
+          *cell = 0ull;
+          const int ir = static_cast<int>(static_cast<unsigned>(w64));
+          const int ii = static_cast<int>(static_cast<unsigned>((w64 - static_cast<unsigned long long>(
+                                                                          static_cast<long long>(ir))) >> 32));
+          acc[j].x += float(ir) * inv;
+          acc[j].y += float(ii) * inv;
+        }
+      }
     }
   };
 
+  for (int k = threadIdx.x; k < 2 * TW * TP; k += GGT) (&acci[0][0])[k] = 0ull;
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int4 un = units[u];
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
-    for (int k = threadIdx.x; k < TW * TP; k += GGT) {
-      accf[k] = make_float2(0.f, 0.f);
-      acci[k] = 0ull;
-    }
-    int q = next_active(un.y, un.z);
+#pragma unroll
+    for (int j = 0; j < NC; ++j) acc[j] = make_float2(0.f, 0.f);
+    int q = next_active(un.y, un.z), buf = 0;
     Item it = make_int4(0, 0, 0, 0);
     if (q < un.z) {
       it = items[idx_list[q]];
       load_raw(it);
-      finish(it, ty, tx);
+      finish(it, ty, tx, 0);
     }
     __syncthreads();
+    bool pend = false;  // a fold of the previous item is due
+    int pbox[4] = {0, 0, 0, 0};
+    float pinv = 0.f;
     while (q < un.z) {
       float bound = 0.f;
       int box[4] = {-TW, -1, -TW, -1};
 #pragma unroll
       for (int w = 0; w < NWV; ++w) {
-        bound += red_b[w];
+        bound += red_b[buf][w];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) box[j] = max(box[j], red_box[j][w]);
+        for (int j = 0; j < 4; ++j) box[j] = max(box[j], red_box[buf][j][w]);
       }
       const int qn = next_active(q + 1, un.z);
       Item itn = make_int4(0, 0, 0, 0);
@@ -354,7 +382,7 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
             int cx, cy;
             kb_weights(crd[k].x, P, wx, cx);
             kb_weights(crd[k].y, P, wy, cy);
-            const int b0 = (cy - ty * T) * TP + (cx - tx * T);
+            unsigned long long* base = &acci[buf][(cy - ty * T) * TP + (cx - tx * T)];
 #pragma unroll
             for (int r = 0; r < KB_J; ++r) {
               const float tr = wy[r] * vr, ti = wy[r] * vi;
@@ -364,52 +392,43 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
                 const unsigned long long w64 =
                     (static_cast<unsigned long long>(static_cast<unsigned>(ii + (ir >> 31))) << 32) |
                     static_cast<unsigned>(ir);
-                atomicAdd(&acci[b0 + r * TP + b], w64);
+                atomicAdd(base + r * TP + b, w64);
               }
             }
           }
         }
       }
-      __syncthreads();
-      if (bound > 0.f) {
-        // fold and clear the footprint box: rows -box[0] .. box[1] + J - 1, same for columns
-        const int r0 = -box[0], c0 = -box[2];
-        const int nr = box[1] + KB_J - r0, nc = box[3] + KB_J - c0;
-        for (int k = threadIdx.x; k < nr * nc; k += GGT) {
-          const int rr = k / nc;
-          const int idx = (r0 + rr) * TP + c0 + (k - rr * nc);
-          const unsigned long long w64 = acci[idx];
-          if (w64) {
-            acci[idx] = 0ull;
-            const int ir = static_cast<int>(static_cast<unsigned>(w64));
-            const int ii = static_cast<int>(static_cast<unsigned>((w64 - static_cast<unsigned long long>(
-                                                                            static_cast<long long>(ir))) >> 32));
-            const float2 a = accf[idx];
-            accf[idx] = make_float2(a.x + float(ir) * inv, a.y + float(ii) * inv);
-          }
-        }
-      }
-      if (qn < un.z) finish(itn, ty, tx);
+      if (pend) fold(buf ^ 1, pbox, pinv);
+      pend = bound > 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) pbox[j] = box[j];
+      pinv = inv;
+      if (qn < un.z) finish(itn, ty, tx, buf ^ 1);
       __syncthreads();
       q = qn;
       it = itn;
+      buf ^= 1;
     }
-    float2* patch = halo + size_t(un.x) * TW * TW;
-    for (int k = threadIdx.x; k < TW * TW; k += GGT) {
-      const int ly = k / TW, lx = k - ly * TW;
-      const float2 a = accf[ly * TP + lx];
+    if (pend) fold(buf ^ 1, pbox, pinv);
+    const int sp = unit_patch != nullptr ? unit_patch[u] : -1;
+    float2* patch = sp >= 0 ? spatch + size_t(sp) * TW * TW : halo + size_t(un.x) * TW * TW;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      const int c = threadIdx.x + j * GGT;
+      if (c >= TW * TW) continue;
+      const int ly = c / TW, lx = c - (c / TW) * TW;
+      const float2 a = acc[j];
       const bool inside = ly >= R0 && ly < R0 + T && lx >= R0 && lx < R0 + T;
-      if (inside) {
+      if (inside && sp < 0) {
         if (a.x != 0.f || a.y != 0.f) {
           float2* g = &grid[size_t(ty * T + ly - R0) * K + tx * T + lx - R0];
           const float2 old = *g;
           *g = make_float2(old.x + a.x, old.y + a.y);
         }
       } else {
-        patch[k] = a;
+        patch[c] = a;  // the ring, or a further slice's whole region
       }
     }
-    __syncthreads();
   }
 }
 
@@ -417,35 +436,54 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
 // within reach of its edges (3 cells from the far edge, 4 from the near edge), clearing
 // every patch cell it reads.  Each patch cell outside its tile lies in exactly one other
 // tile's interior, so it has exactly one reader, and all patches are zero again when the
-// kernel ends (a tile not gridded in a launch therefore contributes nothing).
+// kernel ends (a tile not gridded in a launch therefore contributes nothing).  Where the
+// tile or a neighbour has slice patches (sp_off not null), their cells that fall in this
+// tile's interior are added too, in a fixed order; every slice rewrites its whole patch
+// in each gridding launch, so those are only read.
 template <int T>
-__global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, float2* __restrict__ grid,
-                                                  int K, int tpa) {
+__global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, float2* __restrict__ grid, int K,
+                                                  int tpa, const int* __restrict__ sp_off,
+                                                  const int* __restrict__ sp_list,
+                                                  const float2* __restrict__ spatch) {
   constexpr int TW = T + 8;
   constexpr int R0 = KB_J / 2 - 1;
   const int t = blockIdx.x;
   const int ty = t / tpa, tx = t - (t / tpa) * tpa;
+  bool slices = false;
+  if (sp_off != nullptr)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int nt = ((ty + dy + tpa) & (tpa - 1)) * tpa + ((tx + dx + tpa) & (tpa - 1));
+        slices = slices || sp_off[nt + 1] > sp_off[nt];
+      }
   for (int k = threadIdx.x; k < T * T; k += GT) {
     const int iy = k / T, ix = k - iy * T;
     const bool edge_y = iy < KB_J / 2 || iy >= T - R0, edge_x = ix < KB_J / 2 || ix >= T - R0;
-    if (!edge_y && !edge_x) continue;
+    if (!edge_y && !edge_x && !slices) continue;
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
       for (int dx = -1; dx <= 1; ++dx) {
-        if (dy == 0 && dx == 0) continue;
         // local coordinates of this cell in the neighbour's region
         const int ly = iy - dy * T + R0, lx = ix - dx * T + R0;
         if (ly < 0 || ly >= TW || lx < 0 || lx >= TW) continue;
         const int nt = ((ty + dy + tpa) & (tpa - 1)) * tpa + ((tx + dx + tpa) & (tpa - 1));
-        float2* hp = &halo[size_t(nt) * TW * TW + ly * TW + lx];
-        const float2 h = *hp;
-        if (h.x != 0.f || h.y != 0.f) {
-          acc.x += h.x;
-          acc.y += h.y;
-          *hp = make_float2(0.f, 0.f);
+        if (dy != 0 || dx != 0) {
+          float2* hp = &halo[size_t(nt) * TW * TW + ly * TW + lx];
+          const float2 h = *hp;
+          if (h.x != 0.f || h.y != 0.f) {
+            acc.x += h.x;
+            acc.y += h.y;
+            *hp = make_float2(0.f, 0.f);
+          }
         }
+        if (slices)
+          for (int j = sp_off[nt]; j < sp_off[nt + 1]; ++j) {
+            const float2 h = spatch[size_t(sp_list[j]) * TW * TW + ly * TW + lx];
+            acc.x += h.x;
+            acc.y += h.y;
+          }
       }
     if (acc.x != 0.f || acc.y != 0.f) {
       float2* g = &grid[size_t(ty * T + iy) * K + tx * T + ix];
@@ -488,33 +526,46 @@ int wgs_for(const Plan& p, int units) {
   return units < g ? (units > 0 ? units : 1) : g;
 }
 
+template <int T>
+void launch_halo(const Plan& p, float2* grid, bool sliced, hipStream_t s) {
+  const bool sp = sliced && p.n_spatch > 0;
+  hipLaunchKernelGGL((k_grid_halo<T>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa,
+                     sp ? p.tile_sp_off : nullptr, sp ? p.tile_sp : nullptr, sp ? p.spatch : nullptr);
+}
+
+// units/idx: the plan's tile slices over tile_items (sliced = true) or one block's
+// units over iota (whole tiles).
 template <int T, int MODE>
-int launch_grid(const Plan& p, const int4* units, int nunits, const int* idx, const uint8_t* mask, float2* grid,
-                const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
+int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const int* idx, const uint8_t* mask,
+                float2* grid, const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
                 hipStream_t s, bool with_halo = true) {
   if (nunits > 0) {
     const int g = p.persistent_wgs > 0 ? p.persistent_wgs : device_cus() * 8;
     hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(nunits < g ? nunits : g), dim3(GGT), 0, s, units, nunits, idx,
-                       p.items, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, stats, eps);
+                       p.items, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, stats, eps,
+                       sliced ? p.unit_patch : nullptr, p.spatch);
     RI_LAUNCH_CHECK();
   }
   if (with_halo) {
-    hipLaunchKernelGGL((k_grid_halo<T>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa);
+    launch_halo<T>(p, grid, sliced, s);
     RI_LAUNCH_CHECK();
   }
   return RI_OK;
 }
 
 template <int MODE>
-int grid_units(const Plan& p, const int4* units, int nunits, const int* idx, const uint8_t* mask, float2* grid,
-               const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
+int grid_units(const Plan& p, bool sliced, const int4* units, int nunits, const int* idx, const uint8_t* mask,
+               float2* grid, const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
                hipStream_t s, bool with_halo = true) {
+#define RI_GRID_T(TT) \
+  launch_grid<TT, MODE>(p, sliced, units, nunits, idx, mask, grid, y, e, v, stats, eps, s, with_halo)
   switch (p.tile) {
-    case 16: return launch_grid<16, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s, with_halo);
-    case 32: return launch_grid<32, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s, with_halo);
-    case 64: return launch_grid<64, MODE>(p, units, nunits, idx, mask, grid, y, e, v, stats, eps, s, with_halo);
+    case 16: return RI_GRID_T(16);
+    case 32: return RI_GRID_T(32);
+    case 64: return RI_GRID_T(64);
     default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
   }
+#undef RI_GRID_T
 }
 
 #define RI_TILE_DISPATCH(KERNEL, ...)                                                          \
@@ -579,26 +630,26 @@ int degrid_residual_block(const Plan& p, int block, const float2* grid, const fl
 }
 
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s) {
-  return grid_units<GR_APPLY>(p, p.units, p.n_units, p.tile_items, mask, grid, y, nullptr, nullptr, nullptr,
+  return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.tile_items, mask, grid, y, nullptr, nullptr, nullptr,
                               nullptr, s);
 }
 
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s) {
-  return grid_units<GR_APPLY>(p, p.units, p.n_units, p.tile_items, nullptr, grid, v, nullptr, nullptr, nullptr,
-                              nullptr, s);
+  return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.tile_items, nullptr, grid, v, nullptr, nullptr,
+                              nullptr, nullptr, s);
 }
 
 int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
                  const uint8_t* mask, float2* grid, hipStream_t s) {
-  return grid_units<GR_PROJECT>(p, p.units, p.n_units, p.tile_items, mask, grid, nullptr, e, v, stats, eps, s,
-                                false);
+  return grid_units<GR_PROJECT>(p, true, p.units, p.n_units, p.tile_items, mask, grid, nullptr, e, v, stats, eps,
+                                s, false);
 }
 
 int grid_halo(const Plan& p, float2* grid, hipStream_t s) {
   switch (p.tile) {
-    case 16: hipLaunchKernelGGL((k_grid_halo<16>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa); break;
-    case 32: hipLaunchKernelGGL((k_grid_halo<32>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa); break;
-    case 64: hipLaunchKernelGGL((k_grid_halo<64>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa); break;
+    case 16: launch_halo<16>(p, grid, true, s); break;
+    case 32: launch_halo<32>(p, grid, true, s); break;
+    case 64: launch_halo<64>(p, grid, true, s); break;
     default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
   }
   RI_LAUNCH_CHECK();
@@ -608,7 +659,8 @@ int grid_halo(const Plan& p, float2* grid, hipStream_t s) {
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const double* stats,
                        const double* eps, float2* grid, hipStream_t s) {
   const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
-  return grid_units<GR_PROJECT>(p, p.bunits + a, b - a, p.iota, nullptr, grid, nullptr, e, v, stats, eps, s);
+  return grid_units<GR_PROJECT>(p, false, p.bunits + a, b - a, p.iota, nullptr, grid, nullptr, e, v, stats, eps,
+                                s);
 }
 
 }  // namespace ri

@@ -64,6 +64,10 @@ void destroy_plan(Plan& p) {
   dev_free(p.units);
   dev_free(p.bunits);
   dev_free(p.dunits);
+  dev_free(p.unit_patch);
+  dev_free(p.tile_sp_off);
+  dev_free(p.tile_sp);
+  dev_free(p.spatch);
   dev_free(p.item_part);
   dev_free(p.block_tmp);
   dev_free(p.halo);
@@ -117,6 +121,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   if (p.bin > MAX_BIN) return fail(RI_EINVAL, "bin=%d exceeds %d", p.bin, MAX_BIN);
   p.fft_panel = tune ? tune->fft_panel : 0;
   p.persistent_wgs = tune ? tune->persistent_wgs : 0;
+  p.slice_vis = tune && tune->slice_vis != 0 ? tune->slice_vis : -1;
   p.tpa = p.K / p.tile;
   p.block_off_host.assign(off, off + d + 1);
 
@@ -204,6 +209,57 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
     std::stable_sort(ts.begin(), ts.end(), [&](int a, int b) { return tile_vis[a] > tile_vis[b]; });
     for (int t : ts) units.push_back(make_int4(t, tile_cnt[t], tile_cnt[t + 1], tile_vis[t]));
   }
+  // split dense tiles into slices of whole items
+  std::vector<int> unit_patch;
+  std::vector<std::vector<int>> tile_patches(p.n_tiles);
+  {
+    std::vector<int4> sliced;
+    for (const int4& un : units) {
+      if (p.slice_vis <= 0 || un.w <= p.slice_vis) {
+        sliced.push_back(un);
+        unit_patch.push_back(-1);
+        continue;
+      }
+      int a = un.y, acc = 0;
+      bool first = true;
+      auto emit = [&](int e) {
+        sliced.push_back(make_int4(un.x, a, e, acc));
+        if (first) {
+          unit_patch.push_back(-1);
+        } else {
+          tile_patches[un.x].push_back(p.n_spatch);
+          unit_patch.push_back(p.n_spatch++);
+        }
+        first = false;
+      };
+      for (int q = un.y; q < un.z; ++q) {
+        const int w = items[tile_items[q]].w;
+        if (q > a && acc + w > p.slice_vis) {
+          emit(q);
+          a = q;
+          acc = 0;
+        }
+        acc += w;
+      }
+      emit(un.z);
+    }
+    // densest first
+    std::vector<int> idx(sliced.size());
+    for (size_t k = 0; k < idx.size(); ++k) idx[k] = int(k);
+    std::stable_sort(idx.begin(), idx.end(), [&](int l, int r) { return sliced[l].w > sliced[r].w; });
+    units.clear();
+    std::vector<int> up;
+    for (int k : idx) {
+      units.push_back(sliced[k]);
+      up.push_back(unit_patch[k]);
+    }
+    unit_patch.swap(up);
+  }
+  std::vector<int> tile_sp_off(p.n_tiles + 1, 0), tile_sp;
+  for (int t = 0; t < p.n_tiles; ++t) {
+    tile_sp_off[t + 1] = tile_sp_off[t] + int(tile_patches[t].size());
+    tile_sp.insert(tile_sp.end(), tile_patches[t].begin(), tile_patches[t].end());
+  }
   p.n_units = int(units.size());
   std::vector<int4> dunits;
   for (const int4& un : units) {
@@ -256,6 +312,12 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.units, units.size()));
   RI_TRY(dev_alloc(&p.bunits, bunits.size()));
   RI_TRY(dev_alloc(&p.dunits, dunits.size()));
+  RI_TRY(dev_alloc(&p.unit_patch, unit_patch.size()));
+  RI_TRY(dev_alloc(&p.tile_sp_off, tile_sp_off.size()));
+  if (p.n_spatch > 0) {
+    RI_TRY(dev_alloc(&p.tile_sp, tile_sp.size()));
+    RI_TRY(dev_alloc(&p.spatch, size_t(p.n_spatch) * (p.tile + 8) * (p.tile + 8)));
+  }
   RI_TRY(dev_alloc(&p.item_part, 2 * items.size()));
   RI_TRY(dev_alloc(&p.block_tmp, 2 * size_t(d)));
   RI_TRY(dev_alloc(&p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8)));
@@ -271,6 +333,11 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_HIP(hipMemcpyAsync(p.units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.bunits, bunits.data(), bunits.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.dunits, dunits.data(), dunits.size() * sizeof(int4), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.unit_patch, unit_patch.data(), unit_patch.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.tile_sp_off, tile_sp_off.data(), tile_sp_off.size() * sizeof(int), hipMemcpyHostToDevice,
+                        s));
+  if (p.n_spatch > 0)
+    RI_HIP(hipMemcpyAsync(p.tile_sp, tile_sp.data(), tile_sp.size() * sizeof(int), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.scale, sc.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
   // tiles without visibilities keep an all-zero halo patch forever
   RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8), s));

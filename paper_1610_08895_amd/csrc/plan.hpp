@@ -34,6 +34,7 @@ struct Plan {
   int n_items = 0;
   int fft_panel = 0;
   int persistent_wgs = 0;
+  int slice_vis = -1;  // <= 0: tiles are never split
   KBPoly poly{};
   double poly_err = 0.0;
 
@@ -58,7 +59,15 @@ struct Plan {
   float2* rowbuf = nullptr;   // n * K half-transformed rows
   int* tile_items = nullptr;    // n_items, grouped by tile (all blocks)
   int* iota = nullptr;          // n_items: 0, 1, 2, ...
-  int4* units = nullptr;        // tiles with items, densest first; ranges into tile_items
+  int4* units = nullptr;        // tile slices with items, densest first; ranges into tile_items
+  // A tile with more than slice_vis visibilities is split into slices (units of whole
+  // items); the first accumulates into the grid and the tile's halo patch, each further
+  // one into a whole-region slice patch, which the halo pass adds in a fixed order.
+  int n_spatch = 0;
+  int* unit_patch = nullptr;    // n_units: slice patch of the unit, -1 for a tile's first slice
+  int* tile_sp_off = nullptr;   // n_tiles + 1: slice patches of each tile
+  int* tile_sp = nullptr;       // n_spatch
+  float2* spatch = nullptr;     // n_spatch * (tile + 8)^2
   int4* bunits = nullptr;       // per block; ranges into iota
   int4* dunits = nullptr;       // degridding units, densest first; ranges into tile_items
   double* item_part = nullptr;  // 2 * n_items per-item partial sums of the block norms

@@ -37,14 +37,15 @@ def _mask(mask, d):
 class Plan:
     """Phi = G M F Z for an n x n image, M visibilities in d blocks (Eq. 3, Eq. 8)."""
 
-    def __init__(self, n, uv, block_off, J=8, beta=0.0, tile=0, bin=0, fft_panel=0, persistent_wgs=0):
+    def __init__(self, n, uv, block_off, J=8, beta=0.0, tile=0, bin=0, fft_panel=0, persistent_wgs=0,
+                 slice_vis=0):
         lib = L.load()
         uv = np.ascontiguousarray(uv, dtype=np.float32)
         off = np.ascontiguousarray(block_off, dtype=np.int64)
         if uv.ndim != 2 or uv.shape[1] != 2:
             raise ValueError("uv must be (M, 2)")
         self.n, self.M, self.d = int(n), int(uv.shape[0]), int(off.size - 1)
-        tune = L.Tuning(tile, bin, fft_panel, persistent_wgs)
+        tune = L.Tuning(tile, bin, fft_panel, persistent_wgs, slice_vis)
         h = ctypes.c_void_p()
         L.check(lib.ri_plan_create(ctypes.byref(h), self.n, self.M, uv.ctypes.data, self.d, off.ctypes.data,
                                    J, float(beta), ctypes.byref(tune), _stream()))

@@ -74,6 +74,28 @@ def test_phi_and_adjoint_match_oracle(R, n, M, d, scheme):
     assert rel_l2(xa.cpu().numpy(), xa_ref) < TOL
 
 
+@pytest.mark.parametrize("slice_vis,bin", [(100, 64), (1, 1), (-1, 64)])
+def test_sliced_tiles_match_oracle(R, slice_vis, bin):
+    """Phi^dagger with dense tiles split over several workgroups (slice patches merged by
+    the halo pass), down to one visibility per slice; -1 never splits."""
+    n, M, d = 64, 8192, 4
+    x, uv, off = problem(n, M, d, "annuli", 6)
+    plan = R.Plan(n, uv, off, slice_vis=slice_vis, bin=bin)
+    order = plan.order()
+    meas = Measurement(uv, off, (n, n))
+    rng = np.random.default_rng(7)
+    w = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    mask = np.ones(d, np.uint8)
+    mask[1] = 0
+    wm = w.copy()
+    wm[off[1]:off[2]] = 0
+    xa_ref = meas.phi_adj_real(wm)
+    wt = torch.tensor(to_plan(w, order), dtype=torch.complex64, device="cuda")
+    for _ in range(2):  # slice patches are rewritten by every launch
+        xa = plan.phi_adj(wt, mask=torch.tensor(mask, device="cuda"))
+        assert rel_l2(xa.cpu().numpy(), xa_ref) < TOL
+
+
 def test_phi_masks_touch_only_active_blocks(R):
     n, M, d = 64, 6000, 5
     x, uv, off = problem(n, M, d, "equal", 3)

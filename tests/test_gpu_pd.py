@@ -25,7 +25,7 @@ def R():
     return R
 
 
-def _setup(R, n=64, M=8192, d=4, scheme="equal", seed=2, isnr=30.0, blobs=5, points=10):
+def _setup(R, n=64, M=8192, d=4, scheme="equal", seed=2, isnr=30.0, blobs=5, points=10, **tune):
     x, uv, off = problem(n, M, d, scheme, seed, blobs, points)
     meas = Measurement(uv, off, (n, n))
     osara = OSara(n)
@@ -35,7 +35,7 @@ def _setup(R, n=64, M=8192, d=4, scheme="equal", seed=2, isnr=30.0, blobs=5, poi
     eps = synth.l2_ball_radii(off, sig)
     phin, _ = oracle_phi_norm(meas, synth.power_start(n, seed), tol=0.0, max_it=100)
     prm = opd.default_params(3.0, phin)
-    plan = R.Plan(n, uv, off)
+    plan = R.Plan(n, uv, off, **tune)
     order = plan.order()
     sara = R.Sara(n)
     y_plan = torch.tensor(to_plan(y, order), dtype=torch.complex64, device="cuda")
@@ -52,9 +52,11 @@ def _v_user(pdg, S):
     return to_user(pdg.get(3).cpu().numpy(), S["order"])
 
 
-@pytest.mark.parametrize("plain", [False, True])
-def test_iterations_match_oracle_with_random_masks(R, plain):
-    S = _setup(R, n=64, M=6000, d=5, scheme="lognormal", seed=3)
+@pytest.mark.parametrize("plain,tune", [(False, {}), (True, {}), (False, {"slice_vis": 150, "bin": 64})])
+def test_iterations_match_oracle_with_random_masks(R, plain, tune):
+    """Batched, plain per-block, and batched with every tile split into slices of
+    at most 150 visibilities (items of at most 64)."""
+    S = _setup(R, n=64, M=6000, d=5, scheme="lognormal", seed=3, **tune)
     pdg = _pd(R, S)
     meas, osara = S["meas"], S["osara"]
     yb = opd.split_blocks(meas, S["y"])
