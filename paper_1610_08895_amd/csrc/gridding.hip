@@ -433,20 +433,22 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
 }
 
 // Adds the halo patches of the eight neighbours of each tile into its interior cells
-// within reach of its edges (3 cells from the far edge, 4 from the near edge), clearing
-// every patch cell it reads.  Each patch cell outside its tile lies in exactly one other
-// tile's interior, so it has exactly one reader, and all patches are zero again when the
-// kernel ends (a tile not gridded in a launch therefore contributes nothing).  Where the
+// within reach of its edges (3 cells from the far edge, 4 from the near edge).  Each patch
+// cell outside its tile lies in exactly one other tile's interior, so it has exactly one
+// reader; with CLEAR the reader zeroes it, so that all patches are zero again when the
+// kernel ends (a tile not gridded in a later launch then contributes nothing).  Where the
 // tile or a neighbour has slice patches (sp_off not null), their cells that fall in this
 // tile's interior are added too, in a fixed order; every slice rewrites its whole patch
 // in each gridding launch, so those are only read.
-template <int T>
+template <int T, bool CLEAR>
 __global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, float2* __restrict__ grid, int K,
                                                   int tpa, const int* __restrict__ sp_off,
                                                   const int* __restrict__ sp_list,
                                                   const float2* __restrict__ spatch) {
   constexpr int TW = T + 8;
   constexpr int R0 = KB_J / 2 - 1;
+  constexpr int NEAR = KB_J / 2, FAR = R0;  // edge rows / columns reached from outside
+  constexpr int NE = T * T - (T - NEAR - FAR) * (T - NEAR - FAR);  // edge cells
   const int t = blockIdx.x;
   const int ty = t / tpa, tx = t - (t / tpa) * tpa;
   bool slices = false;
@@ -456,10 +458,22 @@ __global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, flo
         const int nt = ((ty + dy + tpa) & (tpa - 1)) * tpa + ((tx + dx + tpa) & (tpa - 1));
         slices = slices || sp_off[nt + 1] > sp_off[nt];
       }
-  for (int k = threadIdx.x; k < T * T; k += GT) {
-    const int iy = k / T, ix = k - iy * T;
-    const bool edge_y = iy < KB_J / 2 || iy >= T - R0, edge_x = ix < KB_J / 2 || ix >= T - R0;
-    if (!edge_y && !edge_x && !slices) continue;
+  const int ncell = slices ? T * T : NE;
+  for (int k = threadIdx.x; k < ncell; k += GT) {
+    int iy, ix;
+    if (slices) {
+      iy = k / T;
+      ix = k - iy * T;
+    } else if (k < (NEAR + FAR) * T) {  // full edge rows
+      const int r = k / T;
+      iy = r < NEAR ? r : T - NEAR - FAR + r;
+      ix = k - r * T;
+    } else {  // the edge columns of the rows between
+      const int k2 = k - (NEAR + FAR) * T;
+      const int c = k2 % (NEAR + FAR);
+      iy = NEAR + k2 / (NEAR + FAR);
+      ix = c < NEAR ? c : T - NEAR - FAR + c;
+    }
     float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
     for (int dy = -1; dy <= 1; ++dy)
@@ -472,11 +486,9 @@ __global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, flo
         if (dy != 0 || dx != 0) {
           float2* hp = &halo[size_t(nt) * TW * TW + ly * TW + lx];
           const float2 h = *hp;
-          if (h.x != 0.f || h.y != 0.f) {
-            acc.x += h.x;
-            acc.y += h.y;
-            *hp = make_float2(0.f, 0.f);
-          }
+          acc.x += h.x;
+          acc.y += h.y;
+          if (CLEAR && (h.x != 0.f || h.y != 0.f)) *hp = make_float2(0.f, 0.f);
         }
         if (slices)
           for (int j = sp_off[nt]; j < sp_off[nt + 1]; ++j) {
@@ -529,8 +541,14 @@ int wgs_for(const Plan& p, int units) {
 template <int T>
 void launch_halo(const Plan& p, float2* grid, bool sliced, hipStream_t s) {
   const bool sp = sliced && p.n_spatch > 0;
-  hipLaunchKernelGGL((k_grid_halo<T>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa,
-                     sp ? p.tile_sp_off : nullptr, sp ? p.tile_sp : nullptr, sp ? p.spatch : nullptr);
+  if (sliced) {
+    hipLaunchKernelGGL((k_grid_halo<T, false>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa,
+                       sp ? p.tile_sp_off : nullptr, sp ? p.tile_sp : nullptr, sp ? p.spatch : nullptr);
+    p.halo_dirty = true;
+  } else {
+    hipLaunchKernelGGL((k_grid_halo<T, true>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa,
+                       nullptr, nullptr, nullptr);
+  }
 }
 
 // units/idx: the plan's tile slices over tile_items (sliced = true) or one block's
@@ -539,6 +557,10 @@ template <int T, int MODE>
 int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const int* idx, const uint8_t* mask,
                 float2* grid, const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
                 hipStream_t s, bool with_halo = true) {
+  if (!sliced && p.halo_dirty) {  // per-block gridding needs all-zero patches to start from
+    RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * (T + 8) * (T + 8), s));
+    p.halo_dirty = false;
+  }
   if (nunits > 0) {
     const int g = p.persistent_wgs > 0 ? p.persistent_wgs : device_cus() * 8;
     hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(nunits < g ? nunits : g), dim3(GGT), 0, s, units, nunits, idx,

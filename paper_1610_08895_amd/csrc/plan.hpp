@@ -73,6 +73,11 @@ struct Plan {
   double* item_part = nullptr;  // 2 * n_items per-item partial sums of the block norms
   double* block_tmp = nullptr;  // 2 * d
   float2* halo = nullptr;       // n_tiles * (tile + 8)^2 halo patches of the gridding
+  // The batched gridding rewrites the whole ring of every tile with visibilities in each
+  // launch, so its halo pass only reads the patches; the per-block gridding writes some
+  // tiles' patches only, so its halo pass clears what it reads, and the patches are
+  // zeroed first when a batched launch left them filled.
+  mutable bool halo_dirty = false;
   int* active_count = nullptr;
   float* norm_tmp = nullptr;  // n * n scratch for power iterations
   double* dsum = nullptr;     // FP64 reduction scratch
