@@ -37,6 +37,7 @@ namespace ri {
 namespace {
 
 constexpr int GT = 256;    // threads per workgroup
+static_assert(GT / 64 == PART_WAVES, "one norm partial per wavefront of a workgroup");
 constexpr int GGT = 256;  // threads per workgroup of the tile gridding
 
 __device__ __forceinline__ void kb_weights(unsigned packed, const KBPoly& P, float* w, int& cell) {
@@ -78,7 +79,10 @@ struct Pitch {
 };
 
 // Degridding over units {tile, first, end} of the index list idx (items of one tile,
-// several blocks): the tile and its reach are staged once per unit.
+// several blocks): the tile and its reach are staged once per unit, then the waves go
+// through the unit's items without synchronising.  Each thread loads all of its (at most
+// MAX_BIN / GT) visibilities of an item before computing any, and the residual norms of
+// an item are left as one FP64 partial pair per wavefront (part[(item * NWAVES + w) * 2]).
 template <int T, int MODE>
 __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, int nunits,
                                                const int* __restrict__ idx_list, const Item* __restrict__ items,
@@ -87,8 +91,10 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
                                                float2* __restrict__ out, const float2* __restrict__ y,
                                                const float2* __restrict__ v, double* __restrict__ part) {
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
+  constexpr int NV = MAX_BIN / GT;
+  constexpr int NWV = GT / 64;
   __shared__ float2 tile[TW * TP];
-  __shared__ double red[2][GT / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int4 un = units[u];
     bool any = mask == nullptr;
@@ -106,68 +112,69 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
       const int iidx = idx_list[q];
       const Item it = items[iidx];
       if (mask != nullptr && mask[it.x] == 0) continue;
-      double sr = 0.0, se = 0.0;
-      const int end = it.z + it.w;
-      for (int m = it.z + threadIdx.x; m < end; m += GT) {
-        const uint2 c = coord[m];
-        float wx[KB_J], wy[KB_J];
-        int cx, cy;
-        kb_weights(c.x, P, wx, cx);
-        kb_weights(c.y, P, wy, cy);
-        const float2* base = &tile[(cy - ty * T) * TP + (cx - tx * T)];
-        float2 acc = make_float2(0.f, 0.f);
+      uint2 c[NV];
+      float2 yy[NV], vv[NV];
 #pragma unroll
-        for (int ra = 0; ra < KB_J; ++ra) {
-          const float2* row = base + ra * TP;
-          float2 rs = make_float2(0.f, 0.f);
-#pragma unroll
-          for (int b = 0; b < KB_J; ++b) {
-            const float2 g = row[b];
-            rs.x = fmaf(wx[b], g.x, rs.x);
-            rs.y = fmaf(wx[b], g.y, rs.y);
+      for (int k = 0; k < NV; ++k) {
+        const int s = threadIdx.x + k * GT;
+        if (s < it.w) {
+          c[k] = coord[it.z + s];
+          if (MODE == DG_RESIDUAL) {
+            yy[k] = y[it.z + s];
+            vv[k] = v[it.z + s];
           }
-          acc.x = fmaf(wy[ra], rs.x, acc.x);
-          acc.y = fmaf(wy[ra], rs.y, acc.y);
         }
-        if (MODE == DG_APPLY) {
-          out[m] = acc;
-        } else {
-          const float2 yy = y[m], vv = v[m];
-          const float2 e = make_float2(acc.x - yy.x, acc.y - yy.y);
-          const float2 r = make_float2(vv.x + e.x, vv.y + e.y);
-          out[m] = e;
-          sr += double(r.x) * r.x + double(r.y) * r.y;
-          se += double(e.x) * e.x + double(e.y) * e.y;
+      }
+      double sr = 0.0, se = 0.0;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int s = threadIdx.x + k * GT;
+        if (s < it.w) {
+          float wx[KB_J], wy[KB_J];
+          int cx, cy;
+          kb_weights(c[k].x, P, wx, cx);
+          kb_weights(c[k].y, P, wy, cy);
+          const float2* base = &tile[(cy - ty * T) * TP + (cx - tx * T)];
+          float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int ra = 0; ra < KB_J; ++ra) {
+            const float2* row = base + ra * TP;
+            float2 rs = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int b = 0; b < KB_J; ++b) {
+              const float2 g = row[b];
+              rs.x = fmaf(wx[b], g.x, rs.x);
+              rs.y = fmaf(wx[b], g.y, rs.y);
+            }
+            acc.x = fmaf(wy[ra], rs.x, acc.x);
+            acc.y = fmaf(wy[ra], rs.y, acc.y);
+          }
+          if (MODE == DG_APPLY) {
+            out[it.z + s] = acc;
+          } else {
+            const float2 e = make_float2(acc.x - yy[k].x, acc.y - yy[k].y);
+            const float2 r = make_float2(vv[k].x + e.x, vv[k].y + e.y);
+            out[it.z + s] = e;
+            sr += double(r.x) * r.x + double(r.y) * r.y;
+            se += double(e.x) * e.x + double(e.y) * e.y;
+          }
         }
       }
       if (MODE == DG_RESIDUAL) {
         sr = wave_sum(sr);
         se = wave_sum(se);
-        const int wv = threadIdx.x / 64;
-        if ((threadIdx.x & 63) == 0) {
-          red[0][wv] = sr;
-          red[1][wv] = se;
+        if (lane == 0) {
+          part[(size_t(iidx) * NWV + wv) * 2] = sr;
+          part[(size_t(iidx) * NWV + wv) * 2 + 1] = se;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-          for (int k = 0; k < GT / 64; ++k) {
-            a0 += red[0][k];
-            a1 += red[1][k];
-          }
-          part[2 * iidx] = a0;
-          part[2 * iidx + 1] = a1;
-        }
-        __syncthreads();
       }
     }
     __syncthreads();
   }
 }
 
-// stats[2i], stats[2i+1] = sums of the per-item partials of block i, for active blocks;
-// a copy goes to out (if not null), with NaN for inactive blocks.
+// stats[2i], stats[2i+1] = sums of the per-item, per-wavefront partials of block i, for
+// active blocks; a copy goes to out (if not null), with NaN for inactive blocks.
 __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ mask, const int* __restrict__ item_off,
                                                     const double* __restrict__ part, double* __restrict__ stats,
                                                     double* __restrict__ out) {
@@ -182,7 +189,7 @@ __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ 
     return;
   }
   double a0 = 0.0, a1 = 0.0;
-  for (int k = item_off[i] + threadIdx.x; k < item_off[i + 1]; k += GT) {
+  for (int k = item_off[i] * PART_WAVES + threadIdx.x; k < item_off[i + 1] * PART_WAVES; k += GT) {
     a0 += part[2 * k];
     a1 += part[2 * k + 1];
   }
@@ -507,7 +514,7 @@ __global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, flo
 
 __global__ __launch_bounds__(GT) void k_block_sumsq(ItemSource src, const float2* __restrict__ y,
                                                     double* __restrict__ part) {
-  __shared__ double red[GT / 64];
+  const int wv = threadIdx.x >> 6;
   for (int a = blockIdx.x; a < src.count; a += gridDim.x) {
     const int iidx = src.base + a;
     const Item it = src.items[iidx];
@@ -517,15 +524,10 @@ __global__ __launch_bounds__(GT) void k_block_sumsq(ItemSource src, const float2
       acc += double(v.x) * v.x + double(v.y) * v.y;
     }
     acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int k = 0; k < GT / 64; ++k) t += red[k];
-      part[2 * iidx] = t;
-      part[2 * iidx + 1] = 0.0;
+    if ((threadIdx.x & 63) == 0) {
+      part[(size_t(iidx) * PART_WAVES + wv) * 2] = acc;
+      part[(size_t(iidx) * PART_WAVES + wv) * 2 + 1] = 0.0;
     }
-    __syncthreads();
   }
 }
 

@@ -318,7 +318,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
     RI_TRY(dev_alloc(&p.tile_sp, tile_sp.size()));
     RI_TRY(dev_alloc(&p.spatch, size_t(p.n_spatch) * (p.tile + 8) * (p.tile + 8)));
   }
-  RI_TRY(dev_alloc(&p.item_part, 2 * items.size()));
+  RI_TRY(dev_alloc(&p.item_part, 2 * size_t(PART_WAVES) * items.size()));
   RI_TRY(dev_alloc(&p.block_tmp, 2 * size_t(d)));
   RI_TRY(dev_alloc(&p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8)));
   RI_TRY(dev_alloc(&p.norm_tmp, size_t(n) * n));

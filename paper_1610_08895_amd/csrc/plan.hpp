@@ -25,6 +25,7 @@ constexpr unsigned FRAC_MASK = (1u << FRAC_BITS) - 1u;
 using Item = int4;
 constexpr int MAX_BIN = 1024;    // largest `bin` (the gridding kernel stages an item's values in LDS)
 constexpr int DUNIT_VIS = 4096;  // visibilities per degridding unit (several items of one tile)
+constexpr int PART_WAVES = 4;    // FP64 norm partials per work item (one per wavefront)
 
 struct Plan {
   int n = 0, K = 0, J = KB_J, d = 0;
@@ -70,7 +71,7 @@ struct Plan {
   float2* spatch = nullptr;     // n_spatch * (tile + 8)^2
   int4* bunits = nullptr;       // per block; ranges into iota
   int4* dunits = nullptr;       // degridding units, densest first; ranges into tile_items
-  double* item_part = nullptr;  // 2 * n_items per-item partial sums of the block norms
+  double* item_part = nullptr;  // 2 * PART_WAVES * n_items partial sums of the block norms
   double* block_tmp = nullptr;  // 2 * d
   float2* halo = nullptr;       // n_tiles * (tile + 8)^2 halo patches of the gridding
   // The batched gridding rewrites the whole ring of every tile with visibilities in each
