@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="grid tile side (0: library default)")
     ap.add_argument("--bin", type=int, default=0, help="max visibilities per work item (0: library default)")
+    ap.add_argument("--wgs", type=int, default=0, help="workgroups of the persistent kernels (0: library default)")
     ap.add_argument("--slice-vis", type=int, default=0,
                     help="max visibilities per gridding workgroup of one tile (0: default, -1: no split)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -121,7 +122,8 @@ def main():
     t0 = time.time()
     inp = synth.make_inputs(w)
     log(f"inputs {time.time() - t0:.1f}s")
-    plan = R.Plan(w.n, inp.uv, inp.block_off, tile=args.tile, bin=args.bin, slice_vis=args.slice_vis)
+    plan = R.Plan(w.n, inp.uv, inp.block_off, tile=args.tile, bin=args.bin, slice_vis=args.slice_vis,
+                  persistent_wgs=args.wgs)
     order = plan.order()
     log(f"plan {time.time() - t0:.1f}s items={plan.n_items}")
     x_true = torch.tensor(inp.x_true, dtype=torch.float32, device="cuda")

@@ -73,7 +73,7 @@ typedef struct {
   int tile;           /* grid tile side in cells (16, 32 or 64; default 32)            */
   int bin;            /* max visibilities per work item (<= 1024; default 1024)        */
   int fft_panel;      /* columns per workgroup in the column FFT passes (default auto) */
-  int persistent_wgs; /* workgroups of the persistent gather/scatter kernels (auto)    */
+  int persistent_wgs; /* workgroups of the gather/scatter kernels (default: one per unit) */
   int slice_vis;      /* most visibilities one gridding workgroup accumulates for one
                          tile (default and negative: never split); a denser tile is
                          split over several workgroups whose partial tiles the halo

@@ -535,8 +535,12 @@ __global__ void k_take_even(const double* __restrict__ in, double* __restrict__ 
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d; i += gridDim.x * blockDim.x) out[i] = in[2 * i];
 }
 
+// Workgroups of a launch over `units` units: one per unit unless the plan fixes a count
+// (then each takes every gridDim.x-th unit).  With one workgroup per unit, densest first,
+// the hardware dispatcher hands each freed slot the next unit, which balances the uneven
+// units better than any fixed assignment measured.
 int wgs_for(const Plan& p, int units) {
-  int g = p.persistent_wgs > 0 ? p.persistent_wgs : device_cus() * 8;
+  const int g = p.persistent_wgs > 0 ? p.persistent_wgs : units;
   return units < g ? (units > 0 ? units : 1) : g;
 }
 
@@ -564,8 +568,7 @@ int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const
     p.halo_dirty = false;
   }
   if (nunits > 0) {
-    const int g = p.persistent_wgs > 0 ? p.persistent_wgs : device_cus() * 8;
-    hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(nunits < g ? nunits : g), dim3(GGT), 0, s, units, nunits, idx,
+    hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GGT), 0, s, units, nunits, idx,
                        p.items, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, stats, eps,
                        sliced ? p.unit_patch : nullptr, p.spatch);
     RI_LAUNCH_CHECK();

@@ -24,7 +24,7 @@ constexpr unsigned FRAC_MASK = (1u << FRAC_BITS) - 1u;
 // x = block, y = tile (ty * tiles_per_axis + tx), z = first plan position, w = count.
 using Item = int4;
 constexpr int MAX_BIN = 1024;    // largest `bin` (the gridding kernel stages an item's values in LDS)
-constexpr int DUNIT_VIS = 4096;  // visibilities per degridding unit (several items of one tile)
+constexpr int DUNIT_VIS = 2048;  // visibilities per degridding unit (several items of one tile)
 constexpr int PART_WAVES = 4;    // FP64 norm partials per work item (one per wavefront)
 
 struct Plan {
