@@ -221,12 +221,35 @@ enum {
   RI_PD_XTILDE = 1,/* n*n float32                                   */
   RI_PD_S = 2,     /* b*n*n float32                                 */
   RI_PD_V = 3,     /* M complex float32, plan order                 */
-  RI_PD_ITER = 4   /* int64 iteration counter (host buffer)         */
+  RI_PD_ITER = 4,  /* int64 iteration counter (host buffer)         */
+  RI_PD_E = 5      /* M complex float32: G_i b_i - y_i of the last step's active blocks
+                      (read only)                                   */
 };
 /* Copy state `which` to/from buf (device, or host for RI_PD_ITER), `bytes` long.
  * ri_pd_set recomputes sum_i M_i^dagger v~_i from the stored v when V is set. */
 int ri_pd_get(ri_pd pd, int which, void* buf, size_t bytes, hipStream_t stream);
 int ri_pd_set(ri_pd pd, int which, const void* buf, size_t bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * Differentiation of unrolled iterations (masks fixed; the map (tau, sigma) -> x is then
+ * piecewise smooth, the kinks being those of the proximity operators of Sec. III)
+ * ------------------------------------------------------------------------------------ */
+
+/* Reverse (vector-Jacobian) sweep of one ri_pd_step with the pd's tau, sigma, varsigma
+ * and alpha = kappa ||Psi||.  All pointers device.  From the forward step: mask (d, as
+ * given to it), x_new (n*n, x after it), s_new (b*n*n, s after it), v_new and v_old
+ * (M complex, v after and before it), e (M complex, RI_PD_E after it), stats (d x 2
+ * FP64, as it returned them).  Adjoints, updated in place: on entry xbar, xtbar, sbar,
+ * vbar (n*n, n*n, b*n*n, M complex) hold dL/d(x, x~, s, v) after the step, on return
+ * dL/d(x, x~, s, v) before it; pgrad[0], pgrad[1] (FP64) are incremented by the step's
+ * own contributions to dL/dtau and dL/dsigma.  Vector-Jacobian products used: clip ->
+ * 1{|a| < alpha}; step-8 shrink -> (1 - eps/||r||) I + eps r r^T / ||r||^3 outside the
+ * ball (complex as pairs of reals), 0 inside; positivity -> 1{x_new > 0}.  The first
+ * call allocates the sweep's scratch (about 10 n*n floats and M complex values).
+ * Errors: RI_EINVAL (NULL pointer), RI_ENOMEM, RI_EHIP. */
+int ri_pd_step_vjp(ri_pd pd, const uint8_t* mask, const float* x_new, const float* s_new, const float* v_new,
+                   const float* v_old, const float* e, const double* stats, float* xbar, float* xtbar,
+                   float* sbar, float* vbar, double* pgrad, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
  * Adaptive probabilities (Sec. IV)

@@ -20,6 +20,7 @@
 
 #include "handles.hpp"
 #include "sara.hpp"
+#include "vjp.hpp"
 
 struct ri_pd_s {
   ri::Plan* plan = nullptr;
@@ -39,6 +40,14 @@ struct ri_pd_s {
   double* stats = nullptr; // d x 2
   uint8_t* mask_dev = nullptr;
   int64_t iter = 0;
+  // scratch of the reverse sweep, allocated on its first call
+  float* vj_z = nullptr;      // n*n: zbar
+  float* vj_st = nullptr;     // n*n: Psi s_new
+  float* vj_g = nullptr;      // n*n: Re Phi^dagger v_new, then Re Phi_A^dagger rbar
+  float* vj_w = nullptr;      // b*n*n: Psi^dagger zbar
+  float2* vj_phiz = nullptr;  // M: Phi zbar
+  double* vj_part = nullptr;  // dot-product and per-block partials
+  double* vj_coef = nullptr;  // 2 d
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // optional per-stage timing: an event pair around each stage, on the stage's stream
@@ -107,6 +116,13 @@ void destroy_pd(ri_pd_s* P) {
   dev_free(P->eps);
   dev_free(P->stats);
   dev_free(P->mask_dev);
+  dev_free(P->vj_z);
+  dev_free(P->vj_st);
+  dev_free(P->vj_g);
+  dev_free(P->vj_w);
+  dev_free(P->vj_phiz);
+  dev_free(P->vj_part);
+  dev_free(P->vj_coef);
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   if (P->side) (void)hipStreamDestroy(P->side);
@@ -351,6 +367,7 @@ int ri_pd_get(ri_pd P, int which, void* buf, size_t bytes, hipStream_t stream) {
     case RI_PD_XTILDE: src = P->xt; need = N * 4; break;
     case RI_PD_S: src = P->s; need = size_t(P->sara->b) * N * 4; break;
     case RI_PD_V: src = P->v; need = size_t(P->plan->M) * 8; break;
+    case RI_PD_E: src = P->e; need = size_t(P->plan->M) * 8; break;
     case RI_PD_ITER:
       if (bytes != sizeof(int64_t)) return fail(RI_EINVAL, "ITER needs %zu bytes", sizeof(int64_t));
       *static_cast<int64_t*>(buf) = P->iter;
@@ -382,6 +399,48 @@ int ri_pd_set(ri_pd P, int which, const void* buf, size_t bytes, hipStream_t str
   RI_HIP(hipMemcpyAsync(dst, buf, bytes, hipMemcpyDeviceToDevice, stream));
   if (which == RI_PD_V) return ri::refresh_sum(P, stream);
   return RI_OK;
+}
+
+int ri_pd_step_vjp(ri_pd P, const uint8_t* mask, const float* x_new, const float* s_new, const float* v_new,
+                   const float* v_old, const float* e, const double* stats, float* xbar, float* xtbar,
+                   float* sbar, float* vbar, double* pgrad, hipStream_t stream) {
+  if (!P || !mask || !x_new || !s_new || !v_new || !v_old || !e || !stats || !xbar || !xtbar || !sbar || !vbar ||
+      !pgrad)
+    return fail(RI_EINVAL, "NULL argument");
+  const ri::Plan& p = *P->plan;
+  const ri::Sara& S = *P->sara;
+  const int N = p.n * p.n;
+  const size_t NB = size_t(S.b) * N;
+  constexpr int DOT_PARTS = 512;
+  if (!P->vj_z) {
+    const size_t nparts = std::max<size_t>(2 * DOT_PARTS, size_t(p.d) * ri::ball_chunks(p));
+    RI_TRY(ri::dev_alloc(&P->vj_z, size_t(N)));
+    RI_TRY(ri::dev_alloc(&P->vj_st, size_t(N)));
+    RI_TRY(ri::dev_alloc(&P->vj_g, size_t(N)));
+    RI_TRY(ri::dev_alloc(&P->vj_w, NB));
+    RI_TRY(ri::dev_alloc(&P->vj_phiz, size_t(p.M)));
+    RI_TRY(ri::dev_alloc(&P->vj_part, nparts));
+    RI_TRY(ri::dev_alloc(&P->vj_coef, 2 * size_t(p.d)));
+  }
+  const double tau = P->prm.tau, sigma = P->prm.sigma, vs = P->prm.varsigma;
+  const float2* vo = reinterpret_cast<const float2*>(v_old);
+  const float2* ee = reinterpret_cast<const float2*>(e);
+  float2* vb = reinterpret_cast<float2*>(vbar);
+  // steps 17-18
+  RI_TRY(ri::vjp_primal(N, x_new, xbar, xtbar, P->vj_z, stream));
+  RI_TRY(ri::psi_apply(S, s_new, P->vj_st, stream));
+  RI_TRY(ri::phi_adj_apply(p, v_new, P->vj_g, nullptr, stream));
+  RI_TRY(ri::vjp_param_grads(N, P->vj_z, P->vj_st, P->vj_g, tau, sigma, vs, P->vj_part, DOT_PARTS, pgrad, stream));
+  // step 13 (through s~ = Psi s'), then x~bar = Psi abar
+  RI_TRY(ri::psi_adj_apply(S, P->vj_z, P->vj_w, false, 0.f, stream));
+  RI_TRY(ri::vjp_clip(NB, s_new, P->alpha, P->vj_w, float(-tau * sigma), sbar, stream));
+  RI_TRY(ri::psi_apply(S, sbar, xtbar, stream));
+  // steps 5-11 (through g = Re Phi^dagger v'), then x~bar += Re Phi_A^dagger rbar
+  RI_TRY(ri::phi_apply(p, P->vj_z, reinterpret_cast<float*>(P->vj_phiz), nullptr, stream));
+  RI_TRY(ri::vjp_ball(p, mask, vb, P->vj_phiz, float(-tau * vs), vo, ee, stats, P->eps, P->vj_part, P->vj_coef,
+                      stream));
+  RI_TRY(ri::phi_adj_apply(p, vbar, P->vj_g, mask, stream));
+  return ri::axpy(N, 1.f, P->vj_g, xtbar, stream);
 }
 
 }  // extern "C"

@@ -55,6 +55,7 @@ void destroy_plan(Plan& p) {
   dev_free(p.order);
   dev_free(p.items);
   dev_free(p.item_off);
+  dev_free(p.block_off);
   dev_free(p.twiddle);
   dev_free(p.scale);
   dev_free(p.grid);
@@ -303,6 +304,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.order, M));
   RI_TRY(dev_alloc(&p.items, items.size()));
   RI_TRY(dev_alloc(&p.item_off, d + 1));
+  RI_TRY(dev_alloc(&p.block_off, d + 1));
   RI_TRY(dev_alloc(&p.twiddle, K));
   RI_TRY(dev_alloc(&p.scale, n));
   RI_TRY(dev_alloc(&p.grid, size_t(K) * K));
@@ -327,6 +329,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_HIP(hipMemcpyAsync(p.order, p.order_host.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.item_off, p.item_off_host.data(), (d + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.block_off, p.block_off_host.data(), (d + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.twiddle, tw.data(), K * sizeof(float2), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.tile_items, tile_items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.iota, iota.data(), iota.size() * sizeof(int), hipMemcpyHostToDevice, s));

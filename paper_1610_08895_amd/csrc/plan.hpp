@@ -54,6 +54,7 @@ struct Plan {
   int64_t* order = nullptr;   // M, plan position -> user index
   Item* items = nullptr;      // n_items
   int* item_off = nullptr;    // d + 1
+  int64_t* block_off = nullptr;  // d + 1 block offsets (visibilities, plan order = user order per block)
   float2* twiddle = nullptr;  // K forward twiddles exp(-2 pi i k / K)
   float* scale = nullptr;     // n: S along one axis, 1 / phi_hat(l / K)
   float2* grid = nullptr;     // K * K work grid
@@ -118,6 +119,10 @@ int grid_project(const Plan& p, const float2* e, float2* v, const double* stats,
                  const uint8_t* mask, float2* grid, hipStream_t s);
 // Adds the tile halos left by grid_project (which stores them) into the grid.
 int grid_halo(const Plan& p, float2* grid, hipStream_t s);
+// y = Phi x over the blocks with mask[i] != 0 (mask may be null: all); x = Re Phi^dagger y.
+// y is complex interleaved (M), x real (n*n); both use the plan's work grid.
+int phi_apply(const Plan& p, const float* x, float* y, const uint8_t* mask, hipStream_t s);
+int phi_adj_apply(const Plan& p, const float* y, float* x, const uint8_t* mask, hipStream_t s);
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const double* stats,
                        const double* eps, float2* grid, hipStream_t s);
 // grid += G^dagger v over all items (used to rebuild the running sum from scratch).

@@ -199,6 +199,19 @@ class PD:
     def refresh(self):
         L.check(L.load().ri_pd_refresh(self._h, _stream()))
 
+    def step_vjp(self, mask, x_new, s_new, v_new, v_old, e, stats, xbar, xtbar, sbar, vbar, pgrad):
+        """Reverse sweep of one step (ri_pd_step_vjp): the adjoints xbar, xtbar, sbar, vbar
+        are updated in place from after the step to before it; pgrad (2 FP64) accumulates
+        the step's dL/dtau and dL/dsigma."""
+        n, b, M, d = self.plan.n, self.sara.b, self.plan.M, self.plan.d
+        L.check(L.load().ri_pd_step_vjp(
+            self._h, _mask(mask, d), _dev(x_new, torch.float32, (n, n), "x_new"),
+            _dev(s_new, torch.float32, (b, n, n), "s_new"), _dev(v_new, torch.complex64, (M,), "v_new"),
+            _dev(v_old, torch.complex64, (M,), "v_old"), _dev(e, torch.complex64, (M,), "e"),
+            _dev(stats, torch.float64, (d, 2), "stats"), _dev(xbar, torch.float32, (n, n), "xbar"),
+            _dev(xtbar, torch.float32, (n, n), "xtbar"), _dev(sbar, torch.float32, (b, n, n), "sbar"),
+            _dev(vbar, torch.complex64, (M,), "vbar"), _dev(pgrad, torch.float64, (2,), "pgrad"), _stream()))
+
     def timing(self, enable=True):
         """Record a HIP event pair around every stage of the following steps."""
         L.check(L.load().ri_pd_timing(self._h, 1 if enable else 0))
@@ -215,7 +228,7 @@ class PD:
         n = self.plan.n
         return {L.RI_PD_X: ((n, n), torch.float32), L.RI_PD_XTILDE: ((n, n), torch.float32),
                 L.RI_PD_S: ((self.sara.b, n, n), torch.float32),
-                L.RI_PD_V: ((self.plan.M,), torch.complex64)}[which]
+                L.RI_PD_V: ((self.plan.M,), torch.complex64), L.RI_PD_E: ((self.plan.M,), torch.complex64)}[which]
 
     def get(self, which, out=None):
         shape, dt = self._shape(which)
