@@ -99,7 +99,7 @@ def _gpu_grad(R, plan, yp, eps, prm, masks, x, checkpoint):
     err = xtrue - xT.double()
     snr = 20.0 * torch.log10(xtrue.norm() / err.norm())
     snr.backward()
-    return float(snr), params.grad.numpy().copy()
+    return float(snr.detach()), params.grad.numpy().copy()
 
 
 @pytest.mark.parametrize("checkpoint", [5, 1, 10])
