@@ -32,11 +32,19 @@ struct ColCfg {
   static constexpr int NT = K <= 512 ? 256 : 512;
 };
 
+// Twiddles are staged in LDS when the panel and the table fit in 144 KiB together.
+template <int K, int W>
+struct TwLds {
+  static constexpr bool fits = (K * W + K) * 8 <= 144 * 1024;
+  static constexpr int size = fits ? K : 1;
+};
+
 template <int K, int W, int NT>
 __global__ __launch_bounds__(NT) void k_fwd_rows(const float* __restrict__ x, const float* __restrict__ S,
                                                  float2* __restrict__ rows, const float2* __restrict__ tw) {
   constexpr int n = K / 2;
   __shared__ float2 lds[K * W];
+  __shared__ float2 twl[TwLds<K, W>::size];
   const int r0 = blockIdx.x * W;
   auto load = [&](int w, int q) -> float2 {
     const int c = pix_of(q, n, K);
@@ -45,7 +53,7 @@ __global__ __launch_bounds__(NT) void k_fwd_rows(const float* __restrict__ x, co
     return make_float2(x[size_t(r) * n + c] * (S[r] * S[c]), 0.f);
   };
   auto store = [&](int w, int k, float2 v) { rows[size_t(r0 + w) * K + k] = v; };
-  FftPanel<K, W, NT, -1, false>::run(lds, tw, load, store);
+  FftPanel<K, W, NT, -1, false>::template run<TwLds<K, W>::fits>(lds, tw, twl, load, store);
 }
 
 template <int K, int W, int NT>
@@ -53,6 +61,7 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(const float2* __restrict__ rows
                                                  const float2* __restrict__ tw) {
   constexpr int n = K / 2;
   __shared__ float2 lds[K * W];
+  __shared__ float2 twl[TwLds<K, W>::size];
   const int c0 = blockIdx.x * W;
   auto load = [&](int w, int q) -> float2 {
     const int r = pix_of(q, n, K);
@@ -60,7 +69,7 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(const float2* __restrict__ rows
     return rows[size_t(r) * K + c0 + w];
   };
   auto store = [&](int w, int k, float2 v) { grid[size_t(k) * K + c0 + w] = v; };
-  FftPanel<K, W, NT, -1, true>::run(lds, tw, load, store);
+  FftPanel<K, W, NT, -1, true>::template run<TwLds<K, W>::fits>(lds, tw, twl, load, store);
 }
 
 template <int K, int W, int NT>
@@ -68,13 +77,14 @@ __global__ __launch_bounds__(NT) void k_adj_cols(const float2* __restrict__ grid
                                                  const float2* __restrict__ tw) {
   constexpr int n = K / 2;
   __shared__ float2 lds[K * W];
+  __shared__ float2 twl[TwLds<K, W>::size];
   const int c0 = blockIdx.x * W;
   auto load = [&](int w, int k) -> float2 { return grid[size_t(k) * K + c0 + w]; };
   auto store = [&](int w, int q, float2 v) {
     const int r = pix_of(q, n, K);
     if (r >= 0) rows[size_t(r) * K + c0 + w] = v;
   };
-  FftPanel<K, W, NT, +1, true>::run(lds, tw, load, store);
+  FftPanel<K, W, NT, +1, true>::template run<TwLds<K, W>::fits>(lds, tw, twl, load, store);
 }
 
 template <int K, int W, int NT>
@@ -82,6 +92,7 @@ __global__ __launch_bounds__(NT) void k_adj_rows(const float2* __restrict__ rows
                                                  float* __restrict__ x, const float2* __restrict__ tw) {
   constexpr int n = K / 2;
   __shared__ float2 lds[K * W];
+  __shared__ float2 twl[TwLds<K, W>::size];
   const int r0 = blockIdx.x * W;
   auto load = [&](int w, int k) -> float2 { return rows[size_t(r0 + w) * K + k]; };
   auto store = [&](int w, int q, float2 v) {
@@ -91,7 +102,7 @@ __global__ __launch_bounds__(NT) void k_adj_rows(const float2* __restrict__ rows
       x[size_t(r) * n + c] = v.x * (S[r] * S[c]);
     }
   };
-  FftPanel<K, W, NT, +1, false>::run(lds, tw, load, store);
+  FftPanel<K, W, NT, +1, false>::template run<TwLds<K, W>::fits>(lds, tw, twl, load, store);
 }
 
 template <int K>

@@ -102,8 +102,7 @@ struct FftPanel {
   }
 
   template <int R, bool FIRST, bool LAST, class Load, class Store>
-  __device__ static __forceinline__ void pass(float2* lds, const float2* __restrict__ tw, int ns,
-                                              Load& load, Store& store) {
+  __device__ static __forceinline__ void pass(float2* lds, const float2* tw, int ns, Load& load, Store& store) {
     constexpr int JOBS = W * (K / R);
     constexpr int PER = (JOBS + NT - 1) / NT;
     float2 a[PER][R];
@@ -150,9 +149,20 @@ struct FftPanel {
     if (!LAST) __syncthreads();
   }
 
-  // tw: K forward twiddles exp(-2 pi i e / K).
+  // tw: K forward twiddles exp(-2 pi i e / K) in global memory.  With TWL they are first
+  // copied to twl (K entries of LDS) and read from there.
+  template <bool TWL, class Load, class Store>
+  __device__ static void run(float2* lds, const float2* __restrict__ tw, float2* twl, Load& load, Store& store) {
+    if constexpr (TWL) {
+      for (int e = threadIdx.x; e < K; e += NT) twl[e] = tw[e];
+      passes(lds, twl, load, store);  // the first pass's barrier orders these writes before any read
+    } else {
+      passes(lds, tw, load, store);
+    }
+  }
+
   template <class Load, class Store>
-  __device__ static void run(float2* lds, const float2* __restrict__ tw, Load& load, Store& store) {
+  __device__ static __forceinline__ void passes(float2* lds, const float2* tw, Load& load, Store& store) {
     pass<R0, true, false>(lds, tw, 1, load, store);
     int ns = R0;
     if constexpr (NPASS >= 4) {
