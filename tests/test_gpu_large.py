@@ -1,0 +1,116 @@
+"""Full-size GPU checks where the oracle cannot run the whole operator: the 2048^2
+workload (M = 2^24 in 128 log-normal blocks, 10% uniform outliers) and the 512^2
+differentiation workload.
+
+* Phi at 2048^2 on a sample of visibilities, against the oracle evaluated on exactly those
+  visibilities (same image, same grid; relative l2 <= 1e-5);
+* the adjoint identity <Phi x, y> = <x, Re Phi^dagger y> at full size (FP64 dot products of
+  the GPU outputs; a property that holds at any size);
+* three Algorithm 1 iterations at 2048^2 with Eq. 14 probabilities (mean p = 0.25): the
+  invariants x >= 0, |s| <= alpha, inactive blocks' duals untouched, v_i = 0 for blocks
+  inside their ball;
+* the gradient of 1/2 ||Phi x - y||^2 at 512^2, M = 2^20, against the oracle's
+  Re Phi^dagger (Phi x - y).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from helpers import rel_l2, to_plan, to_user
+from oracle import grad as og
+from oracle.measurement import Measurement
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import paper_1610_08895_amd as R
+
+    assert torch.cuda.is_available()
+    return R
+
+
+@pytest.fixture(scope="module")
+def big(R):
+    w = synth.WORKLOADS["n2048_m16m_d128"]
+    inp = synth.make_inputs(w)
+    plan = R.Plan(w.n, inp.uv, inp.block_off)
+    return w, inp, plan
+
+
+def test_phi_sampled_parity_2048(R, big):
+    w, inp, plan = big
+    rng = np.random.default_rng(31)
+    pick = np.sort(rng.choice(w.M, 3000, replace=False))
+    meas = Measurement(inp.uv[pick], np.array([0, pick.size]), (w.n, w.n))
+    y_ref = meas.phi(inp.x_true)
+    y = plan.phi(torch.tensor(inp.x_true, dtype=torch.float32, device="cuda"))
+    y_user = to_user(y.cpu().numpy(), plan.order())
+    assert rel_l2(y_user[pick], y_ref) < 1e-5
+
+
+def test_adjoint_identity_2048(R, big):
+    w, inp, plan = big
+    g = torch.Generator(device="cuda").manual_seed(32)
+    x = torch.rand(w.n, w.n, device="cuda", generator=g)
+    yv = torch.randn(w.M, dtype=torch.complex64, device="cuda", generator=g)
+    lhs = (plan.phi(x).to(torch.complex128).conj() * yv.to(torch.complex128)).sum().real
+    rhs = (x.double() * plan.phi_adj(yv).double()).sum()
+    assert float(abs(lhs - rhs) / abs(rhs)) < 1e-5
+
+
+def test_pd_invariants_2048_adaptive(R, big):
+    from paper_1610_08895_amd import _lib as L
+    from paper_1610_08895_amd.ops import probabilities
+
+    w, inp, plan = big
+    rng = np.random.default_rng(33)
+    y = (rng.standard_normal(w.M) + 1j * rng.standard_normal(w.M)) * 1e-2
+    off = inp.block_off
+    eps = synth.l2_ball_radii(off, 1e-2 * np.sqrt(2.0))
+    eps[::7] *= 10.0  # some blocks start inside their ball
+    yp = torch.tensor(to_plan(y, plan.order()), dtype=torch.complex64, device="cuda")
+    sara = R.Sara(w.n)
+    phin = 4.0 * w.n  # any value keeping the step-size condition
+    tau, kappa = 0.49, 1e-3
+    pd = R.PD(plan, sara, yp, eps, tau, 1.0 / 9.0, 1.0 / phin ** 2, kappa, 3.0, phin)
+    c = np.linspace(0.0, 1.0, plan.d)
+    p, _ = probabilities(c, 0.25 * plan.d, 0.05, 0.5)
+    assert abs(p.sum() - 0.25 * plan.d) < 1e-9
+    u = synth.activity_uniforms(3, plan.d, 34)
+    stats = torch.zeros(plan.d, 2, dtype=torch.float64, device="cuda")
+    alpha = kappa * 3.0
+    for t in range(3):
+        mask = (u[t] < p).astype(np.uint8)
+        v_before = pd.get(L.RI_PD_V).cpu().numpy()
+        pd.step(torch.tensor(mask, device="cuda"), stats)
+        x = pd.get(L.RI_PD_X).cpu().numpy()
+        s = pd.get(L.RI_PD_S).cpu().numpy()
+        v = pd.get(L.RI_PD_V).cpu().numpy()
+        st = stats.cpu().numpy()
+        assert (x >= 0).all()
+        assert np.abs(s).max() <= alpha * (1 + 1e-6)
+        for i in range(plan.d):
+            lo, hi = off[i], off[i + 1]
+            if not mask[i]:
+                assert np.isnan(st[i]).all()
+                assert np.array_equal(v[lo:hi], v_before[lo:hi])   # step 11, bitwise
+            elif np.sqrt(st[i, 0]) <= eps[i]:
+                assert not np.any(v[lo:hi])                          # inside the ball: v_i = 0
+
+
+def test_data_fit_gradient_512(R):
+    from paper_1610_08895_amd import autograd as AG
+
+    w = synth.WORKLOADS["n512_m1m_d32"]
+    inp = synth.make_inputs(w)
+    meas = Measurement(inp.uv, inp.block_off, (w.n, w.n))
+    y, _, _ = synth.add_noise(w, meas.phi(inp.x_true), inp.block_off)
+    x0 = 0.5 * inp.x_true
+    plan = R.Plan(w.n, inp.uv, inp.block_off)
+    xt = torch.tensor(x0, dtype=torch.float32, device="cuda", requires_grad=True)
+    yt = torch.tensor(to_plan(y, plan.order()), dtype=torch.complex64, device="cuda")
+    (0.5 * (AG.phi(plan, xt) - yt).abs().pow(2).sum()).backward()
+    assert rel_l2(xt.grad.cpu().numpy(), og.data_fit_grad(meas, x0, y)) < 1e-5
