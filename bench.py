@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="grid tile side (0: library default)")
     ap.add_argument("--bin", type=int, default=0, help="max visibilities per work item (0: library default)")
     ap.add_argument("--wgs", type=int, default=0, help="workgroups of the persistent kernels (0: library default)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the autotuner's candidates on this workload and use the fastest")
     ap.add_argument("--slice-vis", type=int, default=0,
                     help="max visibilities per gridding workgroup of one tile (0: default, -1: no split)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -122,6 +124,15 @@ def main():
     t0 = time.time()
     inp = synth.make_inputs(w)
     log(f"inputs {time.time() - t0:.1f}s")
+    tuned = None
+    if args.autotune:
+        from paper_1610_08895_amd import autotune
+
+        rng = np.random.default_rng(0)
+        y_probe = rng.standard_normal(w.M) + 1j * rng.standard_normal(w.M)
+        tuned, _ = autotune.tune(w.n, inp.uv, inp.block_off, y_probe, np.full(w.d, 1.0), log=log)
+        args.tile, args.bin, args.slice_vis = tuned["tile"], tuned["bin"], tuned["slice_vis"]
+        log(f"autotuned {tuned} ({time.time() - t0:.1f}s)")
     plan = R.Plan(w.n, inp.uv, inp.block_off, tile=args.tile, bin=args.bin, slice_vis=args.slice_vis,
                   persistent_wgs=args.wgs)
     order = plan.order()
@@ -251,6 +262,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": w.n, "M": w.M, "d": plan.d, "p": 1.0, "tile": plan.tile,
+                   "bin": args.bin or 1024, "slice_vis": args.slice_vis or -1, "autotuned": tuned is not None,
                    "form": "batched persistent kernels" + (" + HIP graph" if use_graph else ""),
                    "kernel": "Kaiser-Bessel 8x8, 2x oversampling", "sara": "Dirac + db1..db8, 4 levels"},
         "phi_gvis_s": round(w.M / phi_ms / 1e6, 2),

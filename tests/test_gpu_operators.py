@@ -194,3 +194,35 @@ def test_bad_arguments_raise(R):
     plan = R.Plan(64, uv, [0, 10])
     with pytest.raises(ValueError):
         plan.phi(torch.zeros(32, 32, device="cuda"))    # wrong image shape (host check)
+
+
+@pytest.mark.parametrize("tile", [16, 64])
+def test_other_tile_sides_match_oracle(R, tile):
+    n, M, d = 128, 20000, 5
+    x, uv, off = problem(n, M, d, "annuli", 14)
+    plan = R.Plan(n, uv, off, tile=tile)
+    assert plan.tile == tile
+    order = plan.order()
+    meas = Measurement(uv, off, (n, n))
+    y = plan.phi(torch.tensor(x, dtype=torch.float32, device="cuda"))
+    assert rel_l2(to_user(y.cpu().numpy(), order), meas.phi(x)) < TOL
+    rng = np.random.default_rng(15)
+    w = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    xa = plan.phi_adj(torch.tensor(to_plan(w, order), dtype=torch.complex64, device="cuda"))
+    assert rel_l2(xa.cpu().numpy(), meas.phi_adj_real(w)) < TOL
+
+
+def test_autotune_picks_a_candidate_and_caches(R, tmp_path):
+    from paper_1610_08895_amd import autotune
+
+    n, M, d = 64, 8192, 4
+    x, uv, off = problem(n, M, d, "equal", 16)
+    rng = np.random.default_rng(17)
+    y = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    eps = np.full(d, 1.0)
+    cands = ({"tile": 32, "bin": 1024, "slice_vis": -1}, {"tile": 16, "bin": 256, "slice_vis": 512})
+    cache = str(tmp_path / "tune.json")
+    best, times = autotune.tune(n, uv, off, y, eps, candidates=cands, steps=3, cache=cache)
+    assert best in [dict(c) for c in cands] and len(times) == 2 and all(t > 0 for t in times.values())
+    again, t2 = autotune.tune(n, uv, off, y, eps, candidates=cands, steps=3, cache=cache)
+    assert again == best and t2 == {}
