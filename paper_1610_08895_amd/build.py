@@ -34,8 +34,8 @@ COMMON = [
 ]
 
 
-# Per-source extra flags.  The gridding kernels round with floor(x + 0.5), which becomes
-# one v_cvt_rpi_i32_f32 only when NaN and infinity need not be honoured; every value they
+# Per-source extra flags.  The gridding kernels round with floor(fma(w, t, c)), which becomes
+# one v_cvt_flr_i32_f32 only when NaN and infinity need not be honoured; every value they
 # round is finite.
 EXTRA = {"gridding.hip": ["-fno-honor-nans", "-fno-honor-infinities"]}
 

@@ -64,9 +64,6 @@ struct ItemSource {
   int base, count;
 };
 
-// Rounds to the nearest integer, halves upwards (one v_cvt_rpi_i32_f32: this file is
-// compiled without NaN and infinity semantics, and the values here are finite).
-__device__ __forceinline__ int round_half_up(float x) { return int(floorf(x + 0.5f)); }
 
 enum { DG_APPLY = 0, DG_RESIDUAL = 1 };
 
@@ -224,9 +221,14 @@ enum { GR_APPLY = 0, GR_PROJECT = 1 };
 // (LDS integer atomics are an order of magnitude faster than LDS float atomics on this
 // hardware), Re in the low and Im in the high 32 bits of one word: every value is scaled
 // by a power of two 2^E chosen from the item's sum of |Re| + |Im|, which bounds any cell's
-// sum, so each field stays below 2^30 in magnitude; the low field's sign borrows from the
-// high field exactly, and decoding subtracts the sign-extended low field.  Rounding (to
-// nearest, halves up) is at most 2^-E-1 per contribution.
+// sum, so each field stays below 2^30 in magnitude.  A contribution (re, im) is added as
+// the 64-bit word re + (im + c) 2^32 with re taken modulo 2^32 in the low half, where c is
+// -1 for the rows whose Re factor is negative and 0 otherwise (folded into the rounding
+// of im): the word then equals re + im' 2^32 exactly with im' = im + c + [re < 0], and since
+// the kernel weights are positive, re < 0 exactly when the row's factor is negative except
+// for products that round to zero, so im' differs from im by at most one unit.  Decoding
+// subtracts the sign-extended low field.  Rounding (to nearest, halves up) is at most
+// 2^-E-1 per contribution for Re and 2^-E-1 + 2^-E for Im.
 //
 // Two integer tiles alternate between items: while item q is accumulated into one, the
 // cells of item q-1's footprint box are folded out of the other (and cleared) into FP32
@@ -393,12 +395,12 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
 #pragma unroll
             for (int r = 0; r < KB_J; ++r) {
               const float tr = wy[r] * vr, ti = wy[r] * vi;
+              const float ci = tr < 0.f ? -0.5f : 0.5f;  // Im rounding offset with the borrow c
 #pragma unroll
               for (int b = 0; b < KB_J; ++b) {
-                const int ir = round_half_up(wx[b] * tr), ii = round_half_up(wx[b] * ti);
+                const int ir = int(floorf(fmaf(wx[b], tr, 0.5f))), ii = int(floorf(fmaf(wx[b], ti, ci)));
                 const unsigned long long w64 =
-                    (static_cast<unsigned long long>(static_cast<unsigned>(ii + (ir >> 31))) << 32) |
-                    static_cast<unsigned>(ir);
+                    (static_cast<unsigned long long>(static_cast<unsigned>(ii)) << 32) | static_cast<unsigned>(ir);
                 atomicAdd(base + r * TP + b, w64);
               }
             }
