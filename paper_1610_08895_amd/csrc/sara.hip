@@ -7,10 +7,11 @@
 // Each workgroup owns an output tile and stages the input it needs in LDS together with
 // its periodic halo (filter length - 2 samples), then runs the row and the column filters
 // from LDS; the filter length is a compile-time constant per basis.  Synthesis computes
-// output pairs (2q, 2q + 1) from the same coefficients a[q - u], d[q - u].  Analysis of level 1 reads x~ once per wavelet from L2; the dual update of step
-// 13, s = clip(s + Psi^dagger x~, -alpha, alpha), is applied as each coefficient is
-// produced.  The last synthesis level sums all bases in registers and applies steps 17-18
-// (primal update and extrapolation) in the same kernel.
+// output pairs (2q, 2q + 1) from the same coefficients a[q - u], d[q - u].  Analysis of
+// level 1 reads x~ once per wavelet from L2; the dual update of step 13,
+// s = clip(s + Psi^dagger x~, -alpha, alpha), is applied as each coefficient is produced,
+// with the old coefficients loaded before the input is staged.  The last synthesis level
+// sums all bases in registers.
 #include <cmath>
 #include <new>
 #include <vector>
@@ -52,6 +53,20 @@ __device__ __forceinline__ void analysis_tile(const DwtArgs& A, const float* __r
   constexpr int RW = 2 * TO + MAX_TAPS - 2; // LDS row stride
   const int n = A.n, m = A.m, mo = A.m / 2, mm = A.m - 1;
   const float* src = A.level == 1 ? A.x : A.tmp + w * A.tmp_stride + A.in_off;
+  float* sb = A.s + size_t(w + A.dirac) * n * n;
+  // the coefficients this thread updates (one output position per thread: TO * TO == ST),
+  // loaded now so that their latency overlaps the staging and the filters
+  static_assert(TO * TO == ST, "one output position per thread");
+  const int pi = threadIdx.x / TO, pj = threadIdx.x - (threadIdx.x / TO) * TO;
+  const int qi = i0 + pi, qj = j0 + pj;
+  const bool mine = qi < mo && qj < mo;
+  float old[4] = {0.f, 0.f, 0.f, 0.f};
+  if (A.clip && mine) {
+    if (A.level == A.levels) old[0] = sb[size_t(qi) * n + qj];
+    old[1] = sb[size_t(qi) * n + mo + qj];
+    old[2] = sb[size_t(mo + qi) * n + qj];
+    old[3] = sb[size_t(mo + qi) * n + mo + qj];
+  }
   for (int idx = threadIdx.x; idx < RE * RE; idx += ST) {
     const int ly = idx / RE, lx = idx - ly * RE;
     in[ly * RW + lx] = src[size_t((2 * i0 + ly) & mm) * m + ((2 * j0 + lx) & mm)];
@@ -70,26 +85,22 @@ __device__ __forceinline__ void analysis_tile(const DwtArgs& A, const float* __r
     hi[rho * TO + j] = d;
   }
   __syncthreads();
-  float* sb = A.s + size_t(w + A.dirac) * n * n;
-  for (int idx = threadIdx.x; idx < TO * TO; idx += ST) {
-    const int i = idx / TO, j = idx - i * TO;
-    const int oi = i0 + i, oj = j0 + j;
-    if (oi >= mo || oj >= mo) continue;
-    float ll = 0.f, lh = 0.f, hl = 0.f, hh = 0.f;
+  if (!mine) return;
+  float ll = 0.f, lh = 0.f, hl = 0.f, hh = 0.f;
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      const float l = lo[(2 * i + t) * TO + j], h = hi[(2 * i + t) * TO + j];
-      ll = fmaf(hw[t], l, ll);
-      lh = fmaf(hw[t], h, lh);
-      hl = fmaf(gw[t], l, hl);
-      hh = fmaf(gw[t], h, hh);
-    }
-    if (A.level < A.levels) A.tmp[w * A.tmp_stride + A.out_off + size_t(oi) * mo + oj] = ll;
-    else put_coef(&sb[size_t(oi) * n + oj], ll, A.clip, A.alpha);
-    put_coef(&sb[size_t(oi) * n + mo + oj], lh, A.clip, A.alpha);
-    put_coef(&sb[size_t(mo + oi) * n + oj], hl, A.clip, A.alpha);
-    put_coef(&sb[size_t(mo + oi) * n + mo + oj], hh, A.clip, A.alpha);
+  for (int t = 0; t < L; ++t) {
+    const float l = lo[(2 * pi + t) * TO + pj], h = hi[(2 * pi + t) * TO + pj];
+    ll = fmaf(hw[t], l, ll);
+    lh = fmaf(hw[t], h, lh);
+    hl = fmaf(gw[t], l, hl);
+    hh = fmaf(gw[t], h, hh);
   }
+  auto put = [&](float* p, float old_v, float v) { *p = A.clip ? clampf(old_v + v, A.alpha) : v; };
+  if (A.level < A.levels) A.tmp[w * A.tmp_stride + A.out_off + size_t(qi) * mo + qj] = ll;
+  else put(&sb[size_t(qi) * n + qj], old[0], ll);
+  put(&sb[size_t(qi) * n + mo + qj], old[1], lh);
+  put(&sb[size_t(mo + qi) * n + qj], old[2], hl);
+  put(&sb[size_t(mo + qi) * n + mo + qj], old[3], hh);
 }
 
 #define RI_SWITCH_L(LEN, CALL)          \
