@@ -119,3 +119,17 @@ def test_unrolled_gradient_matches_finite_differences():
     assert abs(dtau) > 1e-3 and abs(dsig) > 1e-6
     assert dtau == pytest.approx(fd_tau, rel=1e-4)
     assert dsig == pytest.approx(fd_sig, rel=1e-4)
+
+
+def test_stored_512_gradient_agrees_with_its_central_differences():
+    """The stored oracle gradient at 512^2 (M = 2^20, 20 iterations) against the central
+    differences the same script computed (h = 1e-6)."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grad_reference_n512_m1m_d32.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored reference gradient")
+    ref = json.load(open(path))
+    assert ref["dsnr_dtau"] == pytest.approx(ref["fd_dsnr_dtau"], rel=1e-5)
+    assert ref["dsnr_dsigma"] == pytest.approx(ref["fd_dsnr_dsigma"], rel=1e-5)
