@@ -145,31 +145,60 @@ struct IdwtArgs {
 
 constexpr int RS = TS / 2 + MAX_TAPS / 2;  // LDS stride of a staged subband region
 
-// One synthesis level for wavelet w (filters of length L) on output tile (p0, q0):
-// out[2q + r] = sum_u h[2u + r] a[q - u] + g[2u + r] d[q - u] along each axis (the
-// transpose of the analysis), columns (y) first into lo / hi, then rows (x).  Returns
-// through `emit(pl, q, v_even, v_odd)` the output pairs (p0 + pl, q0 + 2q + {0, 1}).
-template <int L, class Emit>
-__device__ __forceinline__ void synthesis_tile(const IdwtArgs& A, const float* __restrict__ hw, int w, int p0,
-                                               int q0, float (*sb)[RS * RS], float* lo, float* hi, Emit& emit) {
-  const float* __restrict__ gw = hw + MAX_TAPS;
-  constexpr int H = L / 2;
-  constexpr int RL = TS / 2 + H;  // coefficient rows / columns the tile reads
+// Coefficients of one synthesis tile: output tile (p0, q0) of wavelet w (half filter
+// length H) reads rows / columns [p0 / 2 - H, p0 / 2 + TS / 2) and [q0 / 2 - H, ...) of
+// each of its four subbands (periodic).  A thread holds elements idx = threadIdx.x + e * ST
+// of the RL x RL region, RL = TS / 2 + H, at (idx / RL, idx % RL).
+constexpr int STAGE_PER = (RS * RS + ST - 1) / ST;
+struct Stage {
+  float v[4][STAGE_PER];
+};
+
+__device__ __forceinline__ void fetch_stage(const IdwtArgs& A, int w, int H, int p0, int q0, Stage& r) {
+  const int RL = TS / 2 + H;
   const int n = A.n, mo = A.m / 2, mk = A.m / 2 - 1;
   const int kr = p0 / 2 - H, kc = q0 / 2 - H;
   const float* sw = A.s + size_t(w + A.dirac) * n * n;
   const bool ll_coef = A.level == A.levels;
   const float* ll = ll_coef ? sw : A.tmp + w * A.tmp_stride + A.ll_off;
   const int ll_stride = ll_coef ? n : mo;
-  for (int idx = threadIdx.x; idx < RL * RL; idx += ST) {
+#pragma unroll
+  for (int e = 0; e < STAGE_PER; ++e) {
+    const int idx = threadIdx.x + e * ST;
+    if (idx >= RL * RL) break;
     const int ky = idx / RL, kx = idx - ky * RL;
     const int gy = (kr + ky) & mk, gx = (kc + kx) & mk;
-    sb[0][ky * RS + kx] = ll[size_t(gy) * ll_stride + gx];
-    sb[1][ky * RS + kx] = sw[size_t(gy) * n + mo + gx];       // low-y, high-x
-    sb[2][ky * RS + kx] = sw[size_t(mo + gy) * n + gx];       // high-y, low-x
-    sb[3][ky * RS + kx] = sw[size_t(mo + gy) * n + mo + gx];  // high-y, high-x
+    r.v[0][e] = ll[size_t(gy) * ll_stride + gx];
+    r.v[1][e] = sw[size_t(gy) * n + mo + gx];       // low-y, high-x
+    r.v[2][e] = sw[size_t(mo + gy) * n + gx];       // high-y, low-x
+    r.v[3][e] = sw[size_t(mo + gy) * n + mo + gx];  // high-y, high-x
   }
-  __syncthreads();
+}
+
+__device__ __forceinline__ void deposit_stage(int H, const Stage& r, float (*sb)[RS * RS]) {
+  const int RL = TS / 2 + H;
+#pragma unroll
+  for (int e = 0; e < STAGE_PER; ++e) {
+    const int idx = threadIdx.x + e * ST;
+    if (idx >= RL * RL) break;
+    const int ky = idx / RL, kx = idx - ky * RL;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sb[c][ky * RS + kx] = r.v[c][e];
+  }
+}
+
+// One synthesis level for one wavelet (filters of length L) on a tile whose coefficients
+// are staged in sb: out[2q + r] = sum_u h[2u + r] a[q - u] + g[2u + r] d[q - u] along each
+// axis (the transpose of the analysis), columns (y) first into lo / hi, then rows (x).
+// Returns through `emit(k, pl, q, v_even, v_odd)` the output pairs (p0 + pl, q0 + 2q +
+// {0, 1}).  Requires sb complete (a barrier after staging); ends after the barrier
+// between its two passes, so sb may be overwritten once it returns.
+template <int L, class Emit>
+__device__ __forceinline__ void synthesis_staged(const float* __restrict__ hw, const float (*sb)[RS * RS],
+                                                 float* lo, float* hi, Emit& emit) {
+  const float* __restrict__ gw = hw + MAX_TAPS;
+  constexpr int H = L / 2;
+  constexpr int RL = TS / 2 + H;
   for (int idx = threadIdx.x; idx < (TS / 2) * RL; idx += ST) {
     const int qy = idx / RL, jl = idx - qy * RL;
     float le = 0.f, lo_ = 0.f, he = 0.f, ho = 0.f;
@@ -217,40 +246,63 @@ __global__ __launch_bounds__(ST) void k_idwt_level(IdwtArgs A, const float* __re
       out[size_t(p) * m + q + 1] = vo;
     }
   };
-#define RI_SYNTH(LL) synthesis_tile<LL>(A, filt + w * FILT_STRIDE, w, p0, q0, sb, lo, hi, emit)
-  RI_SWITCH_L(flen[w], RI_SYNTH)
+  const int L = flen[w];
+  Stage r;
+  fetch_stage(A, w, L / 2, p0, q0, r);
+  deposit_stage(L / 2, r, sb);
+  __syncthreads();
+#define RI_SYNTH(LL) synthesis_staged<LL>(filt + w * FILT_STRIDE, sb, lo, hi, emit)
+  RI_SWITCH_L(L, RI_SYNTH)
 #undef RI_SYNTH
 }
 
+// Last level: each workgroup sums all wavelets' syntheses of its tile in registers.  The
+// coefficients of wavelet w + 1 are loaded into registers while wavelet w is computed and
+// moved to LDS after its column pass, so the loads overlap the arithmetic.
 __global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, const float* __restrict__ filt,
                                                  const int* __restrict__ flen) {
   constexpr int PER = TS * TS / 2 / ST;  // output pairs per thread
   __shared__ float sb[4][RS * RS];
   __shared__ float lo[TS * RS], hi[TS * RS];
   const int p0 = blockIdx.y * TS, q0 = blockIdx.x * TS, n = A.n;
-  float acc_e[PER], acc_o[PER];
+  float acc_e[PER], acc_o[PER], dir[PER][2];
 #pragma unroll
-  for (int k = 0; k < PER; ++k) acc_e[k] = acc_o[k] = 0.f;
+  for (int k = 0; k < PER; ++k) {
+    acc_e[k] = acc_o[k] = 0.f;
+    const int idx = threadIdx.x + k * ST;
+    const int p = p0 + idx / (TS / 2), q = q0 + 2 * (idx % (TS / 2));
+    const bool in = A.dirac && p < n && q < n;
+    dir[k][0] = in ? A.s[size_t(p) * n + q] : 0.f;
+    dir[k][1] = in ? A.s[size_t(p) * n + q + 1] : 0.f;
+  }
   auto emit = [&](int k, int, int, float ve, float vo) {
     acc_e[k] += ve;
     acc_o[k] += vo;
   };
-  for (int w = 0; w < A.nw; ++w) {
-#define RI_SYNTH(LL) synthesis_tile<LL>(A, filt + w * FILT_STRIDE, w, p0, q0, sb, lo, hi, emit)
-    RI_SWITCH_L(flen[w], RI_SYNTH)
-#undef RI_SYNTH
+  if (A.nw > 0) {
+    Stage r;
+    fetch_stage(A, 0, flen[0] / 2, p0, q0, r);
+    deposit_stage(flen[0] / 2, r, sb);
     __syncthreads();
+    for (int w = 0; w < A.nw; ++w) {
+      const int L = flen[w];
+      const bool more = w + 1 < A.nw;
+      const int Hn = more ? flen[w + 1] / 2 : 0;
+      if (more) fetch_stage(A, w + 1, Hn, p0, q0, r);
+#define RI_SYNTH(LL) synthesis_staged<LL>(filt + w * FILT_STRIDE, sb, lo, hi, emit)
+      RI_SWITCH_L(L, RI_SYNTH)
+#undef RI_SYNTH
+      if (more) deposit_stage(Hn, r, sb);
+      __syncthreads();
+    }
   }
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int idx = threadIdx.x + k * ST;
     const int p = p0 + idx / (TS / 2), q = q0 + 2 * (idx % (TS / 2));
     if (p >= n || q >= n) continue;
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const size_t o = size_t(p) * n + q + r;
-      A.x[o] = (r ? acc_o[k] : acc_e[k]) + (A.dirac ? A.s[o] : 0.f);
-    }
+    A.x[size_t(p) * n + q] = acc_e[k] + dir[k][0];
+    A.x[size_t(p) * n + q + 1] = acc_o[k] + dir[k][1];
   }
 }
 
