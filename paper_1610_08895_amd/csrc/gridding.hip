@@ -174,7 +174,8 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
 // active blocks; a copy goes to out (if not null), with NaN for inactive blocks.
 __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ mask, const int* __restrict__ item_off,
                                                     const double* __restrict__ part, double* __restrict__ stats,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, const double* __restrict__ eps,
+                                                    float* __restrict__ shrink) {
   __shared__ double red[2][GT / 64];
   const int i = blockIdx.x;
   if (mask != nullptr && mask[i] == 0) {
@@ -205,6 +206,10 @@ __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ 
     }
     stats[2 * i] = s0;
     stats[2 * i + 1] = s1;
+    if (shrink != nullptr) {  // step 8 through its Moreau form: r max(0, 1 - eps / ||r||)
+      const double ep = eps[i];
+      shrink[i] = s0 > ep * ep ? float(1.0 - ep / sqrt(s0)) : 0.f;
+    }
     if (out != nullptr) {
       out[2 * i] = s0;
       out[2 * i + 1] = s1;
@@ -239,14 +244,23 @@ enum { GR_APPLY = 0, GR_PROJECT = 1 };
 // workgroup alone) is added to the grid and the reach outside it is stored in the tile's
 // halo patch for k_grid_halo (a further slice of a split tile stores its whole region in
 // its slice patch instead).
+// Register budget: four wavefronts per SIMD (<= 128 VGPRs) for tiles up to 32, which
+// measured faster than the three the unconstrained allocation allows; the 64 tile is held
+// to one workgroup per CU by its LDS anyway.
+template <int T>
+constexpr int grid_waves_per_simd() {
+  return T <= 32 ? 4 : 1;
+}
+
 template <int T, int MODE>
-__global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ units, int nunits,
+__global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(const int4* __restrict__ units, int nunits,
                                                    const int* __restrict__ idx_list, const Item* __restrict__ items,
+                                                   const uint32_t* __restrict__ item_box,
                                                    const uint8_t* __restrict__ mask, const uint2* __restrict__ coord,
                                                    float2* __restrict__ grid, float2* __restrict__ halo, int K,
                                                    int tpa, KBPoly P, const float2* __restrict__ y,
                                                    const float2* __restrict__ e, float2* __restrict__ v,
-                                                   const double* __restrict__ stats, const double* __restrict__ eps,
+                                                   const float* __restrict__ shrink,
                                                    const int* __restrict__ unit_patch, float2* __restrict__ spatch) {
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int R0 = KB_J / 2 - 1;  // reach before the tile
@@ -255,7 +269,6 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
   constexpr int NC = (TW * TW + GGT - 1) / GGT;  // region cells per thread
   __shared__ unsigned long long acci[2][TW * TP];
   __shared__ float red_b[2][NWV];
-  __shared__ int red_box[2][4][NWV];  // -row min, row max, -column min, column max
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
   auto next_active = [&](int q, int end) {
@@ -281,15 +294,10 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
       }
     }
   };
-  // values (with the dual update of step 8), the bound and the footprint box into red_*[rb]
-  auto finish = [&](const Item& it, int ty, int tx, int buf) {
-    float shrink = 0.f;
-    if (MODE == GR_PROJECT) {
-      const double nr2 = stats[2 * it.x], ep = eps[it.x];
-      shrink = nr2 > ep * ep ? float(1.0 - ep / sqrt(nr2)) : 0.f;
-    }
+  // values (with the dual update of step 8) and the bound into red_b[buf]
+  auto finish = [&](const Item& it, int buf) {
+    const float sh = MODE == GR_PROJECT ? shrink[it.x] : 0.f;
     float babs = 0.f;
-    int box[4] = {-TW, -1, -TW, -1};
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const int s = threadIdx.x + k * GGT;
@@ -298,36 +306,26 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
         if (MODE == GR_APPLY) {
           val[k] = ra[k];
         } else {
-          const float2 vn = make_float2((ra[k].x + rb[k].x) * shrink, (ra[k].y + rb[k].y) * shrink);
+          const float2 vn = make_float2((ra[k].x + rb[k].x) * sh, (ra[k].y + rb[k].y) * sh);
           v[m] = vn;
           val[k] = make_float2(vn.x - ra[k].x, vn.y - ra[k].y);
         }
         crd[k] = rc[k];
         babs += fabsf(val[k].x) + fabsf(val[k].y);
-        const int ly = int(rc[k].y >> FRAC_BITS) - ty * T, lx = int(rc[k].x >> FRAC_BITS) - tx * T;
-        box[0] = max(box[0], -ly);
-        box[1] = max(box[1], ly);
-        box[2] = max(box[2], -lx);
-        box[3] = max(box[3], lx);
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      babs += __shfl_xor(babs, off, 64);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) box[j] = max(box[j], __shfl_xor(box[j], off, 64));
-    }
-    if (lane == 0) {
-      red_b[buf][wv] = babs;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) red_box[buf][j][wv] = box[j];
-    }
+    for (int off = 32; off > 0; off >>= 1) babs += __shfl_xor(babs, off, 64);
+    if (lane == 0) red_b[buf][wv] = babs;
   };
   // this thread's region cells
   float2 acc[NC];
-  auto fold = [&](int buf, const int* box, float inv) {
-    const int r0 = -box[0], r1 = box[1] + KB_J, c0 = -box[2], c1 = box[3] + KB_J;
+  auto fold = [&](int buf, uint32_t box, float inv) {
+    const int r0 = box & 255u, r1 = int((box >> 8) & 255u) + KB_J;
+    const int c0 = (box >> 16) & 255u, c1 = int(box >> 24) + KB_J;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
+      // rows of this slice of the region's cells (the same for the whole workgroup)
+      if ((j * GGT + GGT - 1) / TW < r0 || (j * GGT) / TW >= r1) continue;
       const int c = threadIdx.x + j * GGT;
       const int ly = c / TW, lx = c - (c / TW) * TW;
       if (c < TW * TW && ly >= r0 && ly < r1 && lx >= c0 && lx < c1) {
@@ -356,21 +354,17 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
     if (q < un.z) {
       it = items[idx_list[q]];
       load_raw(it);
-      finish(it, ty, tx, 0);
+      finish(it, 0);
     }
     __syncthreads();
     bool pend = false;  // a fold of the previous item is due
-    int pbox[4] = {0, 0, 0, 0};
+    uint32_t pbox = 0;
     float pinv = 0.f;
     while (q < un.z) {
       float bound = 0.f;
-      int box[4] = {-TW, -1, -TW, -1};
 #pragma unroll
-      for (int w = 0; w < NWV; ++w) {
-        bound += red_b[buf][w];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) box[j] = max(box[j], red_box[buf][j][w]);
-      }
+      for (int w = 0; w < NWV; ++w) bound += red_b[buf][w];
+      const uint32_t box = item_box[idx_list[q]];
       const int qn = next_active(q + 1, un.z);
       Item itn = make_int4(0, 0, 0, 0);
       if (qn < un.z) {
@@ -409,10 +403,9 @@ __global__ __launch_bounds__(GGT) void k_grid_tiles(const int4* __restrict__ uni
       }
       if (pend) fold(buf ^ 1, pbox, pinv);
       pend = bound > 0.f;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) pbox[j] = box[j];
+      pbox = box;
       pinv = inv;
-      if (qn < un.z) finish(itn, ty, tx, buf ^ 1);
+      if (qn < un.z) finish(itn, buf ^ 1);
       __syncthreads();
       q = qn;
       it = itn;
@@ -563,15 +556,15 @@ void launch_halo(const Plan& p, float2* grid, bool sliced, hipStream_t s) {
 // units over iota (whole tiles).
 template <int T, int MODE>
 int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const int* idx, const uint8_t* mask,
-                float2* grid, const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
-                hipStream_t s, bool with_halo = true) {
+                float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
+                bool with_halo = true) {
   if (!sliced && p.halo_dirty) {  // per-block gridding needs all-zero patches to start from
     RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * (T + 8) * (T + 8), s));
     p.halo_dirty = false;
   }
   if (nunits > 0) {
     hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GGT), 0, s, units, nunits, idx,
-                       p.items, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, stats, eps,
+                       p.items, p.item_box, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, shrink,
                        sliced ? p.unit_patch : nullptr, p.spatch);
     RI_LAUNCH_CHECK();
   }
@@ -584,10 +577,9 @@ int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const
 
 template <int MODE>
 int grid_units(const Plan& p, bool sliced, const int4* units, int nunits, const int* idx, const uint8_t* mask,
-               float2* grid, const float2* y, const float2* e, float2* v, const double* stats, const double* eps,
-               hipStream_t s, bool with_halo = true) {
-#define RI_GRID_T(TT) \
-  launch_grid<TT, MODE>(p, sliced, units, nunits, idx, mask, grid, y, e, v, stats, eps, s, with_halo)
+               float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
+               bool with_halo = true) {
+#define RI_GRID_T(TT) launch_grid<TT, MODE>(p, sliced, units, nunits, idx, mask, grid, y, e, v, shrink, s, with_halo)
   switch (p.tile) {
     case 16: return RI_GRID_T(16);
     case 32: return RI_GRID_T(32);
@@ -607,7 +599,8 @@ int grid_units(const Plan& p, bool sliced, const int4* units, int nunits, const 
 
 }  // namespace
 
-int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s);
+int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s, const double* eps,
+                float* shrink);
 
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s) {
   ItemSource src{p.items, 0, p.n_items};
@@ -619,8 +612,11 @@ int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s) {
   return RI_OK;
 }
 
-int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_block_stats, dim3(p.d), dim3(GT), 0, s, mask, p.item_off, p.item_part, stats, out);
+int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s, const double* eps,
+                float* shrink) {
+  if ((eps == nullptr) != (shrink == nullptr)) return fail(RI_EINVAL, "block_stats: eps and shrink go together");
+  hipLaunchKernelGGL(k_block_stats, dim3(p.d), dim3(GT), 0, s, mask, p.item_off, p.item_part, stats, out, eps,
+                     shrink);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
@@ -660,18 +656,18 @@ int degrid_residual_block(const Plan& p, int block, const float2* grid, const fl
 
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s) {
   return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.tile_items, mask, grid, y, nullptr, nullptr, nullptr,
-                              nullptr, s);
+                              s);
 }
 
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s) {
   return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.tile_items, nullptr, grid, v, nullptr, nullptr,
-                              nullptr, nullptr, s);
+                              nullptr, s);
 }
 
-int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
-                 const uint8_t* mask, float2* grid, hipStream_t s) {
-  return grid_units<GR_PROJECT>(p, true, p.units, p.n_units, p.tile_items, mask, grid, nullptr, e, v, stats, eps,
-                                s, false);
+int grid_project(const Plan& p, const float2* e, float2* v, const float* shrink, const uint8_t* mask, float2* grid,
+                 hipStream_t s) {
+  return grid_units<GR_PROJECT>(p, true, p.units, p.n_units, p.tile_items, mask, grid, nullptr, e, v, shrink, s,
+                                false);
 }
 
 int grid_halo(const Plan& p, float2* grid, hipStream_t s) {
@@ -685,11 +681,10 @@ int grid_halo(const Plan& p, float2* grid, hipStream_t s) {
   return RI_OK;
 }
 
-int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const double* stats,
-                       const double* eps, float2* grid, hipStream_t s) {
+int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const float* shrink, float2* grid,
+                       hipStream_t s) {
   const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
-  return grid_units<GR_PROJECT>(p, false, p.bunits + a, b - a, p.iota, nullptr, grid, nullptr, e, v, stats, eps,
-                                s);
+  return grid_units<GR_PROJECT>(p, false, p.bunits + a, b - a, p.iota, nullptr, grid, nullptr, e, v, shrink, s);
 }
 
 }  // namespace ri

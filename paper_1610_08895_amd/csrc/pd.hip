@@ -38,6 +38,7 @@ struct ri_pd_s {
   float2* sum = nullptr;   // sum_i M_i^dagger v~_i on the K x K grid
   double* eps = nullptr;   // d
   double* stats = nullptr; // d x 2
+  float* shrink = nullptr;  // d: max(0, 1 - eps_i / ||r_i||) of the current step
   uint8_t* mask_dev = nullptr;
   int64_t iter = 0;
   // scratch of the reverse sweep, allocated on its first call
@@ -115,6 +116,7 @@ void destroy_pd(ri_pd_s* P) {
   dev_free(P->sum);
   dev_free(P->eps);
   dev_free(P->stats);
+  dev_free(P->shrink);
   dev_free(P->mask_dev);
   dev_free(P->vj_z);
   dev_free(P->vj_st);
@@ -222,6 +224,7 @@ int ri_pd_create(ri_pd* out, ri_plan plan, ri_sara sara, const float* y, const d
   step(ri::dev_alloc(&P->sum, KK));
   step(ri::dev_alloc(&P->eps, size_t(p.d)));
   step(ri::dev_alloc(&P->stats, 2 * size_t(p.d)));
+  step(ri::dev_alloc(&P->shrink, size_t(p.d)));
   step(ri::dev_alloc(&P->mask_dev, size_t(p.d)));
   if (rc == RI_OK && hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess)
     rc = fail(RI_EHIP, "side stream creation failed");
@@ -278,8 +281,8 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
   }
   RI_STAGE(P, RI_STAGE_DEGRID, stream,
            ri::degrid_residual(p, p.grid, P->y, P->v, P->e, mask, stream));
-  RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, mask, P->stats, stats, stream));
-  RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project(p, P->e, P->v, P->stats, P->eps, mask, P->sum, stream));
+  RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, mask, P->stats, stats, stream, P->eps, P->shrink));
+  RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project(p, P->e, P->v, P->shrink, mask, P->sum, stream));
   RI_STAGE(P, RI_STAGE_GRID_HALO, stream, ri::grid_halo(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows(p, P->g, stream));
@@ -307,11 +310,12 @@ int ri_pd_step_plain(ri_pd P, const uint8_t* mask_host, double* stats, hipStream
     RI_TRY(ri::degrid_residual_block(p, i, p.grid, P->y, P->v, P->e, stream));
   }
   RI_TRY(ri::stage_end(P, RI_STAGE_DEGRID, stream));
-  RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, P->mask_dev, P->stats, stats, stream));
+  RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream,
+           ri::block_stats(p, P->mask_dev, P->stats, stats, stream, P->eps, P->shrink));
   RI_TRY(ri::stage_begin(P, RI_STAGE_GRID, stream));
   for (int i = 0; i < p.d; ++i) {
     if (!mask_host[i]) continue;
-    RI_TRY(ri::grid_project_block(p, i, P->e, P->v, P->stats, P->eps, P->sum, stream));
+    RI_TRY(ri::grid_project_block(p, i, P->e, P->v, P->shrink, P->sum, stream));
   }
   RI_TRY(ri::stage_end(P, RI_STAGE_GRID, stream));
   RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));

@@ -54,6 +54,7 @@ void destroy_plan(Plan& p) {
   dev_free(p.coord);
   dev_free(p.order);
   dev_free(p.items);
+  dev_free(p.item_box);
   dev_free(p.item_off);
   dev_free(p.block_off);
   dev_free(p.twiddle);
@@ -191,6 +192,20 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   }
   p.item_off_host[d] = int(items.size());
   p.n_items = int(items.size());
+  std::vector<uint32_t> item_box(items.size());
+  for (size_t k = 0; k < items.size(); ++k) {
+    const Item& it = items[k];
+    const int oy = (it.y / tpa) * T, ox = (it.y % tpa) * T;
+    int b[4] = {T, -1, T, -1};
+    for (int64_t m = it.z; m < int64_t(it.z) + it.w; ++m) {
+      const int ly = int(coord_sorted[m].y >> FRAC_BITS) - oy, lx = int(coord_sorted[m].x >> FRAC_BITS) - ox;
+      b[0] = std::min(b[0], ly);
+      b[1] = std::max(b[1], ly);
+      b[2] = std::min(b[2], lx);
+      b[3] = std::max(b[3], lx);
+    }
+    item_box[k] = uint32_t(b[0]) | uint32_t(b[1]) << 8 | uint32_t(b[2]) << 16 | uint32_t(b[3]) << 24;
+  }
 
   // items grouped by tile, and tiles grouped into the four gridding colours
   p.n_tiles = tpa * tpa;
@@ -303,6 +318,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.coord, M));
   RI_TRY(dev_alloc(&p.order, M));
   RI_TRY(dev_alloc(&p.items, items.size()));
+  RI_TRY(dev_alloc(&p.item_box, items.size()));
   RI_TRY(dev_alloc(&p.item_off, d + 1));
   RI_TRY(dev_alloc(&p.block_off, d + 1));
   RI_TRY(dev_alloc(&p.twiddle, K));
@@ -328,6 +344,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_HIP(hipMemcpyAsync(p.coord, coord_sorted.data(), M * sizeof(uint2), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.order, p.order_host.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.item_box, item_box.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.item_off, p.item_off_host.data(), (d + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.block_off, p.block_off_host.data(), (d + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.twiddle, tw.data(), K * sizeof(float2), hipMemcpyHostToDevice, s));

@@ -53,6 +53,10 @@ struct Plan {
   uint2* coord = nullptr;     // M packed (x, y) coordinates, plan order
   int64_t* order = nullptr;   // M, plan position -> user index
   Item* items = nullptr;      // n_items
+  // n_items footprint boxes: the smallest and largest row and column of the item's first
+  // taps relative to its tile origin, one byte each (row min, row max, column min, column
+  // max from the low byte up)
+  uint32_t* item_box = nullptr;
   int* item_off = nullptr;    // d + 1
   int64_t* block_off = nullptr;  // d + 1 block offsets (visibilities, plan order = user order per block)
   float2* twiddle = nullptr;  // K forward twiddles exp(-2 pi i k / K)
@@ -98,8 +102,10 @@ int fft_adjoint_rows(const Plan& p, float* x, hipStream_t s);
 
 // ---- launchers implemented in gridding.hip ----
 // stats[2i], stats[2i+1] = per-block sums of the degridding partials, active blocks only;
-// copied to out (may be null) with NaN rows for inactive blocks.
-int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s);
+// copied to out (may be null) with NaN rows for inactive blocks.  With eps and shrink
+// given, also shrink[i] = max(0, 1 - eps_i / ||r_i||) (0 inside the ball) for active blocks.
+int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s,
+                const double* eps = nullptr, float* shrink = nullptr);
 // out[i] = ||y_i||^2 (FP64) for every block.
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s);
 // y = G b for the items of active blocks (operator form).
@@ -113,18 +119,19 @@ int degrid_residual(const Plan& p, const float2* grid, const float2* y, const fl
                     const uint8_t* mask, hipStream_t s);
 int degrid_residual_block(const Plan& p, int block, const float2* grid, const float2* y, const float2* v,
                           float2* e, hipStream_t s);
-// PD projection pass: v_new = (v + e) max(0, 1 - eps/||r||); grid += G^dagger (v_new - v); v = v_new,
-// for the active blocks (tile interiors; grid_halo must follow) or for one block (complete).
-int grid_project(const Plan& p, const float2* e, float2* v, const double* stats, const double* eps,
-                 const uint8_t* mask, float2* grid, hipStream_t s);
+// PD projection pass: v_new = (v + e) shrink_i (shrink from block_stats); grid += G^dagger
+// (v_new - v); v = v_new, for the active blocks (tile interiors; grid_halo must follow) or
+// for one block (complete).
+int grid_project(const Plan& p, const float2* e, float2* v, const float* shrink, const uint8_t* mask, float2* grid,
+                 hipStream_t s);
 // Adds the tile halos left by grid_project (which stores them) into the grid.
 int grid_halo(const Plan& p, float2* grid, hipStream_t s);
 // y = Phi x over the blocks with mask[i] != 0 (mask may be null: all); x = Re Phi^dagger y.
 // y is complex interleaved (M), x real (n*n); both use the plan's work grid.
 int phi_apply(const Plan& p, const float* x, float* y, const uint8_t* mask, hipStream_t s);
 int phi_adj_apply(const Plan& p, const float* y, float* x, const uint8_t* mask, hipStream_t s);
-int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const double* stats,
-                       const double* eps, float2* grid, hipStream_t s);
+int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const float* shrink, float2* grid,
+                       hipStream_t s);
 // grid += G^dagger v over all items (used to rebuild the running sum from scratch).
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s);
 
