@@ -38,8 +38,8 @@ STAGE_KERNEL = {
     "fft_rows": "k_fwd_rows<2048, 1, 256>", "fft_cols": "k_fwd_cols<2048, 8, 512>",
     "degrid": "k_degrid<{T}, 1>", "block_norms": "k_block_stats", "grid": "k_grid_tiles<{T}, 1>",
     "grid_halo": "k_grid_halo<{T}>",
-    "ifft_cols": "k_adj_cols<2048, 8, 512>", "ifft_rows": "k_adj_rows<2048, 1, 256>",
-    "psi_adj": "k_dwt_level (4 launches)", "psi_synth": "k_idwt_level (3 launches) + k_idwt_top", "update": "k_primal_update",
+    "ifft_cols": "k_adj_cols<2048, 8, 512>", "ifft_rows": "k_adj_rows<2048, 1, 256, true> (with steps 17-18)",
+    "psi_adj": "k_dwt_level (4 launches)", "psi_synth": "k_idwt_level (3 launches) + k_idwt_top",
 }
 
 
@@ -60,7 +60,8 @@ def stage_bytes(n, M_active, wavelets=8):
         "degrid": 32 * M_active + 32 * N,            # coords, y, v in; e out; grid read once
         "grid": 32 * M_active + 64 * N,              # coords, e, v in; v out; running grid sum in+out
         "ifft_cols": 32 * N + 16 * N,
-        "ifft_rows": 16 * N + 4 * N,
+        # row pass with steps 17-18: rows, s~ and x in; x and x~ out
+        "ifft_rows": 16 * N + 4 * N * 2 + 4 * N * 2,
         # Psi^dagger + clip: x~ in, s in+out (Dirac and details of every level, LL of the last),
         # LL scratch out+in between levels
         "psi_adj": 4 * N + 8 * N + nw * 8 * (3 * N // 4 + 3 * N // 16 + 3 * N // 64 + 4 * N // 256)
@@ -69,8 +70,6 @@ def stage_bytes(n, M_active, wavelets=8):
         # finest level (LL1 scratch, level-1 details, Dirac in; s~ out)
         "psi_synth": nw * 4 * (3 * N // 16 + 3 * N // 64 + 4 * N // 256) + nw * 4 * 2 * (N // 16 + N // 64)
                      + nw * 4 * (N // 4) + nw * 4 * (N // 4 + 3 * N // 4) + 4 * N + 4 * N,
-        # steps 17-18: s~, g, x in; x, x~ out
-        "update": 4 * N * 3 + 4 * N * 2,
     }
 
 
@@ -183,8 +182,8 @@ def main():
         sol.step(ones)
     stages = sol.pd.stage_times()
     sol.pd.timing(False)
-    mean_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
-    per_iter = {k: v[0] / args.steps for k, v in stages.items()}
+    mean_ms = {k: v[0] / v[1] for k, v in stages.items() if v[1]}
+    per_iter = {k: v[0] / args.steps for k, v in stages.items() if v[1]}
     sb = stage_bytes(w.n, w.M)
     dom = max((k for k in per_iter if k in sb), key=lambda k: per_iter[k])
     alg = sb[dom]

@@ -199,10 +199,11 @@ enum {
   RI_STAGE_GRID = 4,        /* l2-ball shrink, G_i^dagger update, tile interiors (8, 9, 11) */
   RI_STAGE_GRID_HALO = 5,   /* tile halos of the G_i^dagger update                         */
   RI_STAGE_IFFT_COLS = 6,   /* Z^dagger F^dagger, column pass (step 17)                     */
-  RI_STAGE_IFFT_ROWS = 7,   /* Z^dagger F^dagger, row pass (step 17)                        */
+  RI_STAGE_IFFT_ROWS = 7,   /* Z^dagger F^dagger, row pass (step 17); in ri_pd_step it also
+                               applies steps 17-18 to its output                          */
   RI_STAGE_PSI_ADJ = 8,     /* Psi^dagger x~ and dual clip, all levels (step 13)            */
   RI_STAGE_PSI_SYNTH = 9,   /* s~ = Psi s, all levels (step 14)                             */
-  RI_STAGE_UPDATE = 10,     /* steps 17-18, elementwise                                     */
+  RI_STAGE_UPDATE = 10,     /* steps 17-18, elementwise (ri_pd_step_plain only)             */
   RI_STAGE_COUNT = 11
 };
 

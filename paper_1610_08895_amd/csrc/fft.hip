@@ -87,9 +87,11 @@ __global__ __launch_bounds__(NT) void k_adj_cols(const float2* __restrict__ grid
   FftPanel<K, W, NT, +1, true>::template run<TwLds<K, W>::fits>(lds, tw, twl, load, store);
 }
 
-template <int K, int W, int NT>
+// UPD: the output g = Re S (...) feeds steps 17-18 (PrimalUpdate) instead of being stored.
+template <int K, int W, int NT, bool UPD>
 __global__ __launch_bounds__(NT) void k_adj_rows(const float2* __restrict__ rows, const float* __restrict__ S,
-                                                 float* __restrict__ x, const float2* __restrict__ tw) {
+                                                 float* __restrict__ x, const float2* __restrict__ tw,
+                                                 PrimalUpdate u) {
   constexpr int n = K / 2;
   __shared__ float2 lds[K * W];
   __shared__ float2 twl[TwLds<K, W>::size];
@@ -99,7 +101,16 @@ __global__ __launch_bounds__(NT) void k_adj_rows(const float2* __restrict__ rows
     const int c = pix_of(q, n, K);
     if (c >= 0) {
       const int r = r0 + w;
-      x[size_t(r) * n + c] = v.x * (S[r] * S[c]);
+      const size_t o = size_t(r) * n + c;
+      const float g = v.x * (S[r] * S[c]);
+      if (UPD) {
+        const float xo = u.x[o];
+        const float xn = fmaxf(0.f, xo - u.tau * (u.sigma * u.st[o] + u.varsigma * g));
+        u.x[o] = xn;
+        u.xt[o] = 2.f * xn - xo;
+      } else {
+        x[o] = g;
+      }
     }
   };
   FftPanel<K, W, NT, +1, false>::template run<TwLds<K, W>::fits>(lds, tw, twl, load, store);
@@ -135,8 +146,17 @@ int adj_cols_impl(const Plan& p, const float2* grid, float*, hipStream_t s) {
 template <int K>
 int adj_rows_impl(const Plan& p, const float2*, float* x, hipStream_t s) {
   using RC = RowCfg<K>;
-  hipLaunchKernelGGL((k_adj_rows<K, RC::W, RC::NT>), dim3(K / 2 / RC::W), dim3(RC::NT), 0, s, p.rowbuf,
-                     p.scale, x, p.twiddle);
+  hipLaunchKernelGGL((k_adj_rows<K, RC::W, RC::NT, false>), dim3(K / 2 / RC::W), dim3(RC::NT), 0, s, p.rowbuf,
+                     p.scale, x, p.twiddle, PrimalUpdate{});
+  RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+template <int K>
+int adj_rows_update_impl(const Plan& p, const PrimalUpdate& u, hipStream_t s) {
+  using RC = RowCfg<K>;
+  hipLaunchKernelGGL((k_adj_rows<K, RC::W, RC::NT, true>), dim3(K / 2 / RC::W), dim3(RC::NT), 0, s, p.rowbuf,
+                     p.scale, nullptr, p.twiddle, u);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
@@ -170,6 +190,10 @@ int fft_adjoint_cols(const Plan& p, const float2* grid, hipStream_t s) {
 
 int fft_adjoint_rows(const Plan& p, float* x, hipStream_t s) {
   RI_FFT_DISPATCH(adj_rows_impl, p, nullptr, x, s)
+}
+
+int fft_adjoint_rows_update(const Plan& p, const PrimalUpdate& u, hipStream_t s) {
+  RI_FFT_DISPATCH(adj_rows_update_impl, p, u, s)
 }
 
 int fft_forward(const Plan& p, const float* x, float2* grid, hipStream_t s) {

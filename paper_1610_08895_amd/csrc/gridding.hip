@@ -75,18 +75,19 @@ struct Pitch {
   static constexpr int TP = T + 9;
 };
 
-// Degridding over units {tile, first, end} of the index list idx (items of one tile,
+// Degridding over units {tile, first, end} of the unit-ordered items (items of one tile,
 // several blocks): the tile and its reach are staged once per unit, then the waves go
 // through the unit's items without synchronising.  Each thread loads all of its (at most
 // MAX_BIN / GT) visibilities of an item before computing any, and the residual norms of
-// an item are left as one FP64 partial pair per wavefront (part[(item * NWAVES + w) * 2]).
+// an item are left as one FP64 partial pair per wavefront (part[(item * NWAVES + w) * 2],
+// item = its index in block order).
 template <int T, int MODE>
 __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, int nunits,
-                                               const int* __restrict__ idx_list, const Item* __restrict__ items,
-                                               const uint8_t* __restrict__ mask, const uint2* __restrict__ coord,
-                                               const float2* __restrict__ grid, int K, int tpa, KBPoly P,
-                                               float2* __restrict__ out, const float2* __restrict__ y,
-                                               const float2* __restrict__ v, double* __restrict__ part) {
+                                               const Item* __restrict__ items, const uint8_t* __restrict__ mask,
+                                               const uint2* __restrict__ coord, const float2* __restrict__ grid, int K,
+                                               int tpa, KBPoly P, float2* __restrict__ out,
+                                               const float2* __restrict__ y, const float2* __restrict__ v,
+                                               double* __restrict__ part) {
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int NV = MAX_BIN / GT;
   constexpr int NWV = GT / 64;
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int4 un = units[u];
     bool any = mask == nullptr;
-    for (int q = un.y; q < un.z && !any; ++q) any = mask[items[idx_list[q]].x] != 0;
+    for (int q = un.y; q < un.z && !any; ++q) any = mask[items[q].x] != 0;
     if (!any) continue;
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
     const int gy0 = ty * T - (KB_J / 2 - 1), gx0 = tx * T - (KB_J / 2 - 1);
@@ -106,8 +107,7 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
     }
     __syncthreads();
     for (int q = un.y; q < un.z; ++q) {
-      const int iidx = idx_list[q];
-      const Item it = items[iidx];
+      const Item it = items[q];
       if (mask != nullptr && mask[it.x] == 0) continue;
       uint2 c[NV];
       float2 yy[NV], vv[NV];
@@ -161,8 +161,8 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
         sr = wave_sum(sr);
         se = wave_sum(se);
         if (lane == 0) {
-          part[(size_t(iidx) * NWV + wv) * 2] = sr;
-          part[(size_t(iidx) * NWV + wv) * 2 + 1] = se;
+          part[(size_t(it.y) * NWV + wv) * 2] = sr;
+          part[(size_t(it.y) * NWV + wv) * 2 + 1] = se;
         }
       }
     }
@@ -254,7 +254,7 @@ constexpr int grid_waves_per_simd() {
 
 template <int T, int MODE>
 __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(const int4* __restrict__ units, int nunits,
-                                                   const int* __restrict__ idx_list, const Item* __restrict__ items,
+                                                   const Item* __restrict__ items,
                                                    const uint32_t* __restrict__ item_box,
                                                    const uint8_t* __restrict__ mask, const uint2* __restrict__ coord,
                                                    float2* __restrict__ grid, float2* __restrict__ halo, int K,
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
   auto next_active = [&](int q, int end) {
-    while (q < end && mask != nullptr && mask[items[idx_list[q]].x] == 0) ++q;
+    while (q < end && mask != nullptr && mask[items[q].x] == 0) ++q;
     return q;
   };
   // operands of the current item, and the raw loads of the next one
@@ -349,13 +349,19 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
 #pragma unroll
     for (int j = 0; j < NC; ++j) acc[j] = make_float2(0.f, 0.f);
-    int q = next_active(un.y, un.z), buf = 0;
-    Item it = make_int4(0, 0, 0, 0);
-    if (q < un.z) {
-      it = items[idx_list[q]];
-      load_raw(it);
-      finish(it, 0);
+    // the first item's loads are issued before its block's mask is read (units are never
+    // empty, and a masked item's loads are simply not used)
+    int q = un.y, buf = 0;
+    Item it = items[q];
+    load_raw(it);
+    if (mask != nullptr && mask[it.x] == 0) {
+      q = next_active(q + 1, un.z);
+      if (q < un.z) {
+        it = items[q];
+        load_raw(it);
+      }
     }
+    if (q < un.z) finish(it, 0);
     __syncthreads();
     bool pend = false;  // a fold of the previous item is due
     uint32_t pbox = 0;
@@ -364,11 +370,11 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
       float bound = 0.f;
 #pragma unroll
       for (int w = 0; w < NWV; ++w) bound += red_b[buf][w];
-      const uint32_t box = item_box[idx_list[q]];
+      const uint32_t box = item_box[it.y];
       const int qn = next_active(q + 1, un.z);
       Item itn = make_int4(0, 0, 0, 0);
       if (qn < un.z) {
-        itn = items[idx_list[qn]];
+        itn = items[qn];
         load_raw(itn);
       }
       // 2^E with bound * 2^E <= 2^30 (bound * 1.0001 guards the bound's own rounding)
@@ -411,8 +417,8 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
       it = itn;
       buf ^= 1;
     }
-    if (pend) fold(buf ^ 1, pbox, pinv);
     const int sp = unit_patch != nullptr ? unit_patch[u] : -1;
+    if (pend) fold(buf ^ 1, pbox, pinv);
     float2* patch = sp >= 0 ? spatch + size_t(sp) * TW * TW : halo + size_t(un.x) * TW * TW;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
@@ -552,10 +558,10 @@ void launch_halo(const Plan& p, float2* grid, bool sliced, hipStream_t s) {
   }
 }
 
-// units/idx: the plan's tile slices over tile_items (sliced = true) or one block's
-// units over iota (whole tiles).
+// units/items: the plan's tile slices over titems (sliced = true) or one block's units
+// over items (whole tiles).
 template <int T, int MODE>
-int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const int* idx, const uint8_t* mask,
+int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const Item* items, const uint8_t* mask,
                 float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
                 bool with_halo = true) {
   if (!sliced && p.halo_dirty) {  // per-block gridding needs all-zero patches to start from
@@ -563,8 +569,8 @@ int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const
     p.halo_dirty = false;
   }
   if (nunits > 0) {
-    hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GGT), 0, s, units, nunits, idx,
-                       p.items, p.item_box, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, shrink,
+    hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GGT), 0, s, units, nunits, items,
+                       p.item_box, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, shrink,
                        sliced ? p.unit_patch : nullptr, p.spatch);
     RI_LAUNCH_CHECK();
   }
@@ -576,10 +582,10 @@ int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const
 }
 
 template <int MODE>
-int grid_units(const Plan& p, bool sliced, const int4* units, int nunits, const int* idx, const uint8_t* mask,
+int grid_units(const Plan& p, bool sliced, const int4* units, int nunits, const Item* items, const uint8_t* mask,
                float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
                bool with_halo = true) {
-#define RI_GRID_T(TT) launch_grid<TT, MODE>(p, sliced, units, nunits, idx, mask, grid, y, e, v, shrink, s, with_halo)
+#define RI_GRID_T(TT) launch_grid<TT, MODE>(p, sliced, units, nunits, items, mask, grid, y, e, v, shrink, s, with_halo)
   switch (p.tile) {
     case 16: return RI_GRID_T(16);
     case 32: return RI_GRID_T(32);
@@ -623,7 +629,7 @@ int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, 
 
 int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* mask, hipStream_t s) {
   const dim3 grid_dim(wgs_for(p, p.n_dunits));
-#define ARGS p.dunits, p.n_dunits, p.tile_items, p.items, mask, p.coord, grid, p.K, p.tpa, p.poly, y, \
+#define ARGS p.dunits, p.n_dunits, p.titems, mask, p.coord, grid, p.K, p.tpa, p.poly, y, \
              (const float2*)nullptr, (const float2*)nullptr, (double*)nullptr
   RI_TILE_DISPATCH(k_degrid, DG_APPLY)
 #undef ARGS
@@ -634,7 +640,7 @@ int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* ma
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
                     const uint8_t* mask, hipStream_t s) {
   const dim3 grid_dim(wgs_for(p, p.n_dunits));
-#define ARGS p.dunits, p.n_dunits, p.tile_items, p.items, mask, p.coord, grid, p.K, p.tpa, p.poly, e, y, v, \
+#define ARGS p.dunits, p.n_dunits, p.titems, mask, p.coord, grid, p.K, p.tpa, p.poly, e, y, v, \
              p.item_part
   RI_TILE_DISPATCH(k_degrid, DG_RESIDUAL)
 #undef ARGS
@@ -646,7 +652,7 @@ int degrid_residual_block(const Plan& p, int block, const float2* grid, const fl
                           float2* e, hipStream_t s) {
   const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
   const dim3 grid_dim(wgs_for(p, b - a));
-#define ARGS p.bunits + a, b - a, p.iota, p.items, (const uint8_t*)nullptr, p.coord, grid, p.K, p.tpa, p.poly, e, \
+#define ARGS p.bunits + a, b - a, p.items, (const uint8_t*)nullptr, p.coord, grid, p.K, p.tpa, p.poly, e, \
              y, v, p.item_part
   RI_TILE_DISPATCH(k_degrid, DG_RESIDUAL)
 #undef ARGS
@@ -655,18 +661,18 @@ int degrid_residual_block(const Plan& p, int block, const float2* grid, const fl
 }
 
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s) {
-  return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.tile_items, mask, grid, y, nullptr, nullptr, nullptr,
+  return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.titems, mask, grid, y, nullptr, nullptr, nullptr,
                               s);
 }
 
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s) {
-  return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.tile_items, nullptr, grid, v, nullptr, nullptr,
+  return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.titems, nullptr, grid, v, nullptr, nullptr,
                               nullptr, s);
 }
 
 int grid_project(const Plan& p, const float2* e, float2* v, const float* shrink, const uint8_t* mask, float2* grid,
                  hipStream_t s) {
-  return grid_units<GR_PROJECT>(p, true, p.units, p.n_units, p.tile_items, mask, grid, nullptr, e, v, shrink, s,
+  return grid_units<GR_PROJECT>(p, true, p.units, p.n_units, p.titems, mask, grid, nullptr, e, v, shrink, s,
                                 false);
 }
 
@@ -684,7 +690,7 @@ int grid_halo(const Plan& p, float2* grid, hipStream_t s) {
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const float* shrink, float2* grid,
                        hipStream_t s) {
   const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
-  return grid_units<GR_PROJECT>(p, false, p.bunits + a, b - a, p.iota, nullptr, grid, nullptr, e, v, shrink, s);
+  return grid_units<GR_PROJECT>(p, false, p.bunits + a, b - a, p.items, nullptr, grid, nullptr, e, v, shrink, s);
 }
 
 }  // namespace ri

@@ -9,7 +9,8 @@
 // s~ = Psi s.
 // The two branches depend only on x~ of the previous iteration (the paper runs them
 // concurrently); the batched step forks the sparsity branch onto a side stream after the
-// forward FFT and joins before the last kernel, the elementwise steps 17-18.
+// forward FFT and joins before the last kernel, the adjoint row pass, which applies the
+// elementwise steps 17-18 to g as it produces it (g is never stored).
 //
 // The running sum is kept in FP32 and updated by differences; ri_pd_refresh (and setting
 // V) rebuilds it from the stored v, bounding accumulated rounding.
@@ -285,10 +286,10 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
   RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project(p, P->e, P->v, P->shrink, mask, P->sum, stream));
   RI_STAGE(P, RI_STAGE_GRID_HALO, stream, ri::grid_halo(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
-  RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows(p, P->g, stream));
-  // join, then the primal update
+  // join, then the adjoint row pass with steps 17-18 fused into its output
   if (fork) RI_HIP(hipStreamWaitEvent(stream, P->ev_join, 0));
-  RI_TRY(ri::primal_update(P, stream));
+  const ri::PrimalUpdate upd{P->st, P->x, P->xt, float(P->prm.tau), float(P->prm.sigma), float(P->prm.varsigma)};
+  RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows_update(p, upd, stream));
   P->iter += 1;
   return RI_OK;
 }

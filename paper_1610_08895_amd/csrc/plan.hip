@@ -61,8 +61,7 @@ void destroy_plan(Plan& p) {
   dev_free(p.scale);
   dev_free(p.grid);
   dev_free(p.rowbuf);
-  dev_free(p.tile_items);
-  dev_free(p.iota);
+  dev_free(p.titems);
   dev_free(p.units);
   dev_free(p.bunits);
   dev_free(p.dunits);
@@ -304,8 +303,10 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
     }
   }
   p.bunit_off_host[d] = int(bunits.size());
-  std::vector<int> iota(items.size());
-  for (size_t k = 0; k < iota.size(); ++k) iota[k] = int(k);
+  // device copies: y = index in block order
+  std::vector<Item> items_dev(items), titems(items.size());
+  for (size_t k = 0; k < items.size(); ++k) items_dev[k].y = int(k);
+  for (size_t q = 0; q < items.size(); ++q) titems[q] = items_dev[tile_items[q]];
 
   std::vector<float2> tw(K);
   for (int k = 0; k < K; ++k) {
@@ -325,8 +326,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.scale, n));
   RI_TRY(dev_alloc(&p.grid, size_t(K) * K));
   RI_TRY(dev_alloc(&p.rowbuf, size_t(n) * K));
-  RI_TRY(dev_alloc(&p.tile_items, items.size()));
-  RI_TRY(dev_alloc(&p.iota, items.size()));
+  RI_TRY(dev_alloc(&p.titems, items.size()));
   RI_TRY(dev_alloc(&p.units, units.size()));
   RI_TRY(dev_alloc(&p.bunits, bunits.size()));
   RI_TRY(dev_alloc(&p.dunits, dunits.size()));
@@ -343,13 +343,12 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.dsum, SUMSQ_SCRATCH));
   RI_HIP(hipMemcpyAsync(p.coord, coord_sorted.data(), M * sizeof(uint2), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.order, p.order_host.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  RI_HIP(hipMemcpyAsync(p.items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.items, items_dev.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.titems, titems.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.item_box, item_box.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.item_off, p.item_off_host.data(), (d + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.block_off, p.block_off_host.data(), (d + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.twiddle, tw.data(), K * sizeof(float2), hipMemcpyHostToDevice, s));
-  RI_HIP(hipMemcpyAsync(p.tile_items, tile_items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice, s));
-  RI_HIP(hipMemcpyAsync(p.iota, iota.data(), iota.size() * sizeof(int), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.units, units.data(), units.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.bunits, bunits.data(), bunits.size() * sizeof(int4), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.dunits, dunits.data(), dunits.size() * sizeof(int4), hipMemcpyHostToDevice, s));

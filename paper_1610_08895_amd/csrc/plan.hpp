@@ -22,6 +22,8 @@ constexpr unsigned FRAC_MASK = (1u << FRAC_BITS) - 1u;
 
 // A work item: up to `bin` visibilities of one block that fall in one grid tile.
 // x = block, y = tile (ty * tiles_per_axis + tx), z = first plan position, w = count.
+// The device copies carry in y the item's index in block order instead (which indexes the
+// per-item arrays); the tile comes from the unit that lists the item.
 using Item = int4;
 constexpr int MAX_BIN = 1024;    // largest `bin` (the gridding kernel stages an item's values in LDS)
 constexpr int DUNIT_VIS = 2048;  // visibilities per degridding unit (several items of one tile)
@@ -52,7 +54,8 @@ struct Plan {
   // device
   uint2* coord = nullptr;     // M packed (x, y) coordinates, plan order
   int64_t* order = nullptr;   // M, plan position -> user index
-  Item* items = nullptr;      // n_items
+  Item* items = nullptr;      // n_items, block order (y = own index)
+  Item* titems = nullptr;     // n_items grouped by tile (all blocks), y = index in block order
   // n_items footprint boxes: the smallest and largest row and column of the item's first
   // taps relative to its tile origin, one byte each (row min, row max, column min, column
   // max from the low byte up)
@@ -63,9 +66,7 @@ struct Plan {
   float* scale = nullptr;     // n: S along one axis, 1 / phi_hat(l / K)
   float2* grid = nullptr;     // K * K work grid
   float2* rowbuf = nullptr;   // n * K half-transformed rows
-  int* tile_items = nullptr;    // n_items, grouped by tile (all blocks)
-  int* iota = nullptr;          // n_items: 0, 1, 2, ...
-  int4* units = nullptr;        // tile slices with items, densest first; ranges into tile_items
+  int4* units = nullptr;        // tile slices with items, densest first; ranges into titems
   // A tile with more than slice_vis visibilities is split into slices (units of whole
   // items); the first accumulates into the grid and the tile's halo patch, each further
   // one into a whole-region slice patch, which the halo pass adds in a fixed order.
@@ -74,8 +75,8 @@ struct Plan {
   int* tile_sp_off = nullptr;   // n_tiles + 1: slice patches of each tile
   int* tile_sp = nullptr;       // n_spatch
   float2* spatch = nullptr;     // n_spatch * (tile + 8)^2
-  int4* bunits = nullptr;       // per block; ranges into iota
-  int4* dunits = nullptr;       // degridding units, densest first; ranges into tile_items
+  int4* bunits = nullptr;       // per block; ranges into items
+  int4* dunits = nullptr;       // degridding units, densest first; ranges into titems
   double* item_part = nullptr;  // 2 * PART_WAVES * n_items partial sums of the block norms
   double* block_tmp = nullptr;  // 2 * d
   float2* halo = nullptr;       // n_tiles * (tile + 8)^2 halo patches of the gridding
@@ -99,6 +100,16 @@ int fft_forward_rows(const Plan& p, const float* x, hipStream_t s);
 int fft_forward_cols(const Plan& p, float2* grid, hipStream_t s);
 int fft_adjoint_cols(const Plan& p, const float2* grid, hipStream_t s);
 int fft_adjoint_rows(const Plan& p, float* x, hipStream_t s);
+// Steps 17-18 fused into the adjoint row pass: with g = Re S Z^dagger F^dagger of the
+// plan's row buffer, x <- max(0, x - tau (sigma st + varsigma g)) and xt = 2 x_new - x_old,
+// elementwise over the n x n image (g itself is not stored).
+struct PrimalUpdate {
+  const float* st;
+  float* x;
+  float* xt;
+  float tau, sigma, varsigma;
+};
+int fft_adjoint_rows_update(const Plan& p, const PrimalUpdate& u, hipStream_t s);
 
 // ---- launchers implemented in gridding.hip ----
 // stats[2i], stats[2i+1] = per-block sums of the degridding partials, active blocks only;
