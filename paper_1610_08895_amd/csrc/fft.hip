@@ -32,6 +32,13 @@ struct ColCfg {
   static constexpr int NT = K <= 512 ? 256 : 512;
 };
 
+// Column panel of workgroup b of nb: consecutive blocks go round-robin to the eight XCDs,
+// so neighbouring panels, which share 128-byte rows of the grid, are given to blocks on
+// the same XCD (and its L2) when nb is a multiple of 8.
+__device__ __forceinline__ int panel_of(int b, int nb) {
+  return nb % 8 == 0 ? (b % 8) * (nb / 8) + b / 8 : b;
+}
+
 // Twiddles are staged in LDS when the panel and the table fit in 144 KiB together.
 template <int K, int W>
 struct TwLds {
@@ -62,7 +69,7 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(const float2* __restrict__ rows
   constexpr int n = K / 2;
   __shared__ float2 lds[K * W];
   __shared__ float2 twl[TwLds<K, W>::size];
-  const int c0 = blockIdx.x * W;
+  const int c0 = panel_of(blockIdx.x, gridDim.x) * W;
   auto load = [&](int w, int q) -> float2 {
     const int r = pix_of(q, n, K);
     if (r < 0) return make_float2(0.f, 0.f);
@@ -78,7 +85,7 @@ __global__ __launch_bounds__(NT) void k_adj_cols(const float2* __restrict__ grid
   constexpr int n = K / 2;
   __shared__ float2 lds[K * W];
   __shared__ float2 twl[TwLds<K, W>::size];
-  const int c0 = blockIdx.x * W;
+  const int c0 = panel_of(blockIdx.x, gridDim.x) * W;
   auto load = [&](int w, int k) -> float2 { return grid[size_t(k) * K + c0 + w]; };
   auto store = [&](int w, int q, float2 v) {
     const int r = pix_of(q, n, K);
