@@ -29,6 +29,23 @@ constexpr int TS = 32;   // synthesis: outputs per axis per workgroup
 
 __device__ __forceinline__ float clampf(float v, float a) { return fminf(fmaxf(v, -a), a); }
 
+// Tile (tx, ty) of this workgroup in a gridDim.x x gridDim.y tile grid.  Consecutive
+// workgroups go round-robin to the eight XCDs, so with a row-major order neighbouring tiles,
+// whose staged regions overlap, would sit on different XCDs; when the row count is a
+// multiple of 8, each XCD takes a band of whole tile rows instead, and the overlaps are
+// fetched once into its L2.
+__device__ __forceinline__ void band_tile(int& tx, int& ty) {
+  const int nx = gridDim.x, ny = gridDim.y;
+  if (ny % 8 != 0) {
+    tx = blockIdx.x;
+    ty = blockIdx.y;
+    return;
+  }
+  const int b = blockIdx.x + nx * blockIdx.y, i = b / 8;
+  ty = (b % 8) * (ny / 8) + i / nx;
+  tx = i - (i / nx) * nx;
+}
+
 struct DwtArgs {
   const float* x;  // level-1 input (n x n)
   float* tmp;
@@ -121,7 +138,9 @@ __global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, const float* __rest
   __shared__ float in[RW * RW];
   __shared__ float lo[RW * TO], hi[RW * TO];
   const int n = A.n;
-  const int i0 = blockIdx.y * TO, j0 = blockIdx.x * TO;
+  int tx, ty;
+  band_tile(tx, ty);
+  const int i0 = ty * TO, j0 = tx * TO;
   const int z = blockIdx.z;
   if (z == A.nw) {  // Dirac basis at level 1: coefficient = pixel
     for (int idx = threadIdx.x; idx < 4 * TO * TO; idx += ST) {
@@ -237,7 +256,9 @@ __global__ __launch_bounds__(ST) void k_idwt_level(IdwtArgs A, const float* __re
   __shared__ float sb[4][RS * RS];
   __shared__ float lo[TS * RS], hi[TS * RS];
   const int w = blockIdx.z;
-  const int p0 = blockIdx.y * TS, q0 = blockIdx.x * TS, m = A.m;
+  int tx, ty;
+  band_tile(tx, ty);
+  const int p0 = ty * TS, q0 = tx * TS, m = A.m;
   float* out = A.tmp + w * A.tmp_stride + A.out_off;
   auto emit = [&](int, int pl, int qx, float ve, float vo) {
     const int p = p0 + pl, q = q0 + 2 * qx;
@@ -264,7 +285,9 @@ __global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, const float* __rest
   constexpr int PER = TS * TS / 2 / ST;  // output pairs per thread
   __shared__ float sb[4][RS * RS];
   __shared__ float lo[TS * RS], hi[TS * RS];
-  const int p0 = blockIdx.y * TS, q0 = blockIdx.x * TS, n = A.n;
+  int tx, ty;
+  band_tile(tx, ty);
+  const int p0 = ty * TS, q0 = tx * TS, n = A.n;
   float acc_e[PER], acc_o[PER], dir[PER][2];
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
