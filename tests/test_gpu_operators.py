@@ -137,7 +137,9 @@ def test_gpu_adjoint_dot_product(R):
     assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
 
 
-@pytest.mark.parametrize("n,levels", [(64, 4), (32, 4), (128, 3), (16, 1)])
+# 256 and 512 include tile grids whose row counts are multiples of 8 (the kernels' XCD
+# band mapping of tiles is then active)
+@pytest.mark.parametrize("n,levels", [(64, 4), (32, 4), (128, 3), (16, 1), (256, 2), (512, 4)])
 def test_psi_and_adjoint_match_oracle(R, n, levels):
     rng = np.random.default_rng(n)
     x = rng.standard_normal((n, n))
