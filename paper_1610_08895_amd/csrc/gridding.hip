@@ -270,7 +270,8 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
                                                    int tpa, KBPoly P, const float2* __restrict__ y,
                                                    const float2* __restrict__ e, float2* __restrict__ v,
                                                    const float* __restrict__ shrink,
-                                                   const int* __restrict__ unit_patch, float2* __restrict__ spatch) {
+                                                   const int* __restrict__ unit_patch, float2* __restrict__ spatch,
+                                                   int fresh) {
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int R0 = KB_J / 2 - 1;  // reach before the tile
   constexpr int NV = MAX_BIN / GGT;
@@ -437,8 +438,10 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
       const float2 a = acc[j];
       const bool inside = ly >= R0 && ly < R0 + T && lx >= R0 && lx < R0 + T;
       if (inside && sp < 0) {
-        if (a.x != 0.f || a.y != 0.f) {
-          float2* g = &grid[size_t(ty * T + ly - R0) * K + tx * T + lx - R0];
+        float2* g = &grid[size_t(ty * T + ly - R0) * K + tx * T + lx - R0];
+        if (fresh) {
+          *g = a;  // the workgroup owns the interior: no read of the old value
+        } else if (a.x != 0.f || a.y != 0.f) {
           const float2 old = *g;
           *g = make_float2(old.x + a.x, old.y + a.y);
         }
@@ -569,18 +572,35 @@ void launch_halo(const Plan& p, float2* grid, bool sliced, hipStream_t s) {
 
 // units/items: the plan's tile slices over titems (sliced = true) or one block's units
 // over items (whole tiles).
+// Zeroes the interiors of the plan's tiles without visibilities (a fresh gridding writes
+// every other tile's interior itself).
+template <int T>
+__global__ __launch_bounds__(GT) void k_zero_tiles(float2* __restrict__ grid, int K, int tpa,
+                                                   const int* __restrict__ tiles) {
+  const int t = tiles[blockIdx.x];
+  const int ty = t / tpa, tx = t - (t / tpa) * tpa;
+  for (int c = threadIdx.x; c < T * T; c += GT)
+    grid[size_t(ty * T + c / T) * K + tx * T + c % T] = make_float2(0.f, 0.f);
+}
+
+// fresh: the launch overwrites the grid (tile interiors stored, tiles without
+// visibilities zeroed) instead of adding into it.
 template <int T, int MODE>
 int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const Item* items, const uint8_t* mask,
                 float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
-                bool with_halo = true) {
+                bool with_halo = true, bool fresh = false) {
   if (!sliced && p.halo_dirty) {  // per-block gridding needs all-zero patches to start from
     RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * (T + 8) * (T + 8), s));
     p.halo_dirty = false;
   }
+  if (fresh && p.n_empty > 0) {
+    hipLaunchKernelGGL((k_zero_tiles<T>), dim3(p.n_empty), dim3(GT), 0, s, grid, p.K, p.tpa, p.empty_tiles);
+    RI_LAUNCH_CHECK();
+  }
   if (nunits > 0) {
     hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GGT), 0, s, units, nunits, items,
                        p.item_box, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, shrink,
-                       sliced ? p.unit_patch : nullptr, p.spatch);
+                       sliced ? p.unit_patch : nullptr, p.spatch, fresh ? 1 : 0);
     RI_LAUNCH_CHECK();
   }
   if (with_halo) {
@@ -593,8 +613,9 @@ int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const
 template <int MODE>
 int grid_units(const Plan& p, bool sliced, const int4* units, int nunits, const Item* items, const uint8_t* mask,
                float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
-               bool with_halo = true) {
-#define RI_GRID_T(TT) launch_grid<TT, MODE>(p, sliced, units, nunits, items, mask, grid, y, e, v, shrink, s, with_halo)
+               bool with_halo = true, bool fresh = false) {
+#define RI_GRID_T(TT) \
+  launch_grid<TT, MODE>(p, sliced, units, nunits, items, mask, grid, y, e, v, shrink, s, with_halo, fresh)
   switch (p.tile) {
     case 16: return RI_GRID_T(16);
     case 32: return RI_GRID_T(32);
@@ -671,12 +692,12 @@ int degrid_residual_block(const Plan& p, int block, const float2* grid, const fl
 
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s) {
   return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.titems, mask, grid, y, nullptr, nullptr, nullptr,
-                              s);
+                              s, true, true);
 }
 
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s) {
   return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.titems, nullptr, grid, v, nullptr, nullptr,
-                              nullptr, s);
+                              nullptr, s, true, true);
 }
 
 int grid_project(const Plan& p, const float2* e, float2* v, const float* shrink, const uint8_t* mask, float2* grid,

@@ -138,7 +138,6 @@ void destroy_pd(ri_pd_s* P) {
 
 int refresh_sum(ri_pd_s* P, hipStream_t s) {
   const Plan& p = *P->plan;
-  RI_TRY(zero_c64(P->sum, size_t(p.K) * p.K, s));
   return grid_all(p, P->v, P->sum, s);
 }
 

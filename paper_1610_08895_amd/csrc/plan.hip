@@ -72,6 +72,7 @@ void destroy_plan(Plan& p) {
   dev_free(p.item_part);
   dev_free(p.block_tmp);
   dev_free(p.halo);
+  dev_free(p.empty_tiles);
   dev_free(p.norm_tmp);
   dev_free(p.dsum);
 }
@@ -216,6 +217,10 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   for (int t = 0; t < p.n_tiles; ++t) tile_cnt[t + 1] += tile_cnt[t];
   std::vector<int> tile_items(items.size()), fill(tile_cnt.begin(), tile_cnt.end() - 1);
   for (int k = 0; k < int(items.size()); ++k) tile_items[fill[items[k].y]++] = k;
+  std::vector<int> empty_tiles;
+  for (int t = 0; t < p.n_tiles; ++t)
+    if (tile_vis[t] == 0) empty_tiles.push_back(t);
+  p.n_empty = int(empty_tiles.size());
   std::vector<int4> units, bunits;
   {
     std::vector<int> ts;
@@ -339,6 +344,11 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.item_part, 2 * size_t(PART_WAVES) * items.size()));
   RI_TRY(dev_alloc(&p.block_tmp, 2 * size_t(d)));
   RI_TRY(dev_alloc(&p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8)));
+  if (p.n_empty > 0) {
+    RI_TRY(dev_alloc(&p.empty_tiles, empty_tiles.size()));
+    RI_HIP(hipMemcpyAsync(p.empty_tiles, empty_tiles.data(), empty_tiles.size() * sizeof(int), hipMemcpyHostToDevice,
+                          s));
+  }
   RI_TRY(dev_alloc(&p.norm_tmp, size_t(n) * n));
   RI_TRY(dev_alloc(&p.dsum, SUMSQ_SCRATCH));
   RI_HIP(hipMemcpyAsync(p.coord, coord_sorted.data(), M * sizeof(uint2), hipMemcpyHostToDevice, s));
@@ -372,7 +382,6 @@ int phi_apply(const Plan& p, const float* x, float* y, const uint8_t* mask, hipS
 }
 
 int phi_adj_apply(const Plan& p, const float* y, float* x, const uint8_t* mask, hipStream_t s) {
-  RI_TRY(zero_c64(p.grid, size_t(p.K) * p.K, s));
   RI_TRY(grid_apply(p, reinterpret_cast<const float2*>(y), mask, p.grid, s));
   return fft_adjoint(p, p.grid, x, s);
 }

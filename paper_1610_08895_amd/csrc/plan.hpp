@@ -80,6 +80,8 @@ struct Plan {
   double* item_part = nullptr;  // 2 * PART_WAVES * n_items partial sums of the block norms
   double* block_tmp = nullptr;  // 2 * d
   float2* halo = nullptr;       // n_tiles * (tile + 8)^2 halo patches of the gridding
+  int n_empty = 0;
+  int* empty_tiles = nullptr;   // n_empty tiles without visibilities
   // The batched gridding rewrites the whole ring of every tile with visibilities in each
   // launch, so its halo pass only reads the patches; the per-block gridding writes some
   // tiles' patches only, so its halo pass clears what it reads, and the patches are
@@ -121,7 +123,8 @@ int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, 
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s);
 // y = G b for the items of active blocks (operator form).
 int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* mask, hipStream_t s);
-// grid += G^dagger y for the active blocks (operator form; grid zeroed by the caller).
+// grid = G^dagger y for the active blocks (operator form; the whole grid is written, tiles
+// without visibilities set to zero).
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s);
 // PD residual pass: e = G b - y, r = v + e; stats[2i] = ||r_i||^2, stats[2i+1] = ||e_i||^2 for the
 // blocks whose items are processed (per-item partial sums, then a per-block reduction).
@@ -143,7 +146,7 @@ int phi_apply(const Plan& p, const float* x, float* y, const uint8_t* mask, hipS
 int phi_adj_apply(const Plan& p, const float* y, float* x, const uint8_t* mask, hipStream_t s);
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const float* shrink, float2* grid,
                        hipStream_t s);
-// grid += G^dagger v over all items (used to rebuild the running sum from scratch).
+// grid = G^dagger v over all items (rebuilds the running sum from scratch).
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s);
 
 // ---- reductions (reduce.hip) ----
