@@ -329,17 +329,17 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   };
   // this thread's region cells
   float2 acc[NC];
+  // Only the slices of cells that meet the box's rows are visited (a test that is the same
+  // for the whole workgroup); cells outside the box were never touched and read as zero.
+  static_assert(TP == TW + 1, "cell c of the region sits at c + c / TW in the pitched tile");
   auto fold = [&](int buf, uint32_t box, float inv) {
     const int r0 = box & 255u, r1 = int((box >> 8) & 255u) + KB_J;
-    const int c0 = (box >> 16) & 255u, c1 = int(box >> 24) + KB_J;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      // rows of this slice of the region's cells (the same for the whole workgroup)
       if ((j * GGT + GGT - 1) / TW < r0 || (j * GGT) / TW >= r1) continue;
       const int c = threadIdx.x + j * GGT;
-      const int ly = c / TW, lx = c - (c / TW) * TW;
-      if (c < TW * TW && ly >= r0 && ly < r1 && lx >= c0 && lx < c1) {
-        unsigned long long* cell = &acci[buf][ly * TP + lx];
+      if (c < TW * TW) {
+        unsigned long long* cell = &acci[buf][c + c / TW];
         const unsigned long long w64 = *cell;
         if (w64) {
           *cell = 0ull;
