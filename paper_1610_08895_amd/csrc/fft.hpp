@@ -3,7 +3,8 @@
 // A workgroup transforms W independent sequences of length K held in LDS.  The first
 // pass reads its inputs straight from a load functor (global memory) and the last pass
 // writes straight to a store functor, so each element crosses HBM once each way.  Passes
-// are radix-8 except a leading radix-2 or radix-4 one when log2 K is not a multiple of 3.
+// are radix-RB (8, or 16 when the panel has at least one radix-16 job per thread) except
+// a leading one of radix 2^(log2 K mod log2 RB) when log2 K is not a multiple of log2 RB.
 //
 // Pass with radix R after stride NS (the product of the radices already applied): job j
 // of a sequence reads a[r] = X[j + r K/R], multiplies a[r] by w^{r k}, w = exp(s 2 pi i /
@@ -72,18 +73,54 @@ __device__ __forceinline__ void dft8(float2* a) {
   a[7] = csub(e3, o3);
 }
 
+// 16-point DFT as 4 x 4: index n = 4 n1 + n2, k = k1 + 4 k2; 4-point DFTs over n1, the
+// twiddles exp(DIR 2 pi i n2 k1 / 16), 4-point DFTs over n2, then the transpose.
+template <int DIR>
+__device__ __forceinline__ void dft16(float2* a) {
+  constexpr float C1 = 0.92387953251128675613f;  // cos(pi / 8)
+  constexpr float S1 = 0.38268343236508977173f;  // sin(pi / 8)
+  constexpr float H = 0.70710678118654752440f;
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<DIR>(a[n2], a[4 + n2], a[8 + n2], a[12 + n2]);
+  // slot 4 k1 + n2 now holds the k1-th output of column n2; twiddle by w^(n2 k1)
+  auto tw = [](float2 v, float c, float sn) {  // v * (c + DIR i sn)
+    return DIR < 0 ? make_float2(v.x * c + v.y * sn, v.y * c - v.x * sn)
+                   : make_float2(v.x * c - v.y * sn, v.y * c + v.x * sn);
+  };
+  a[5] = tw(a[5], C1, S1);     // w^1
+  a[6] = tw(a[6], H, H);       // w^2
+  a[7] = tw(a[7], S1, C1);     // w^3
+  a[9] = tw(a[9], H, H);       // w^2
+  a[10] = mul_i<DIR>(a[10]);   // w^4
+  a[11] = tw(a[11], -H, H);    // w^6
+  a[13] = tw(a[13], S1, C1);   // w^3
+  a[14] = tw(a[14], -H, H);    // w^6
+  a[15] = tw(a[15], -C1, -S1); // w^9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<DIR>(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+  // slot 4 k1 + k2 holds output k1 + 4 k2
+  float2 t[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) t[k] = a[4 * (k & 3) + (k >> 2)];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) a[k] = t[k];
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft(float2* a) {
   if constexpr (R == 2) dft2<DIR>(a);
   else if constexpr (R == 4) dft4<DIR>(a[0], a[1], a[2], a[3]);
-  else dft8<DIR>(a);
+  else if constexpr (R == 8) dft8<DIR>(a);
+  else dft16<DIR>(a);
 }
 
 template <int K, int W, int NT, int DIR, bool WFAST>
 struct FftPanel {
   static constexpr int LOGK = clog2(K);
-  static constexpr int R0 = (LOGK % 3 == 0) ? 8 : (LOGK % 3 == 1 ? 2 : 4);
-  static constexpr int NPASS = (LOGK % 3 == 0) ? LOGK / 3 : LOGK / 3 + 1;
+  static constexpr int RB = W * (K / 16) >= NT ? 16 : 8;  // radix of the passes after the first
+  static constexpr int LB = clog2(RB);
+  static constexpr int R0 = LOGK % LB == 0 ? RB : (1 << (LOGK % LB));
+  static constexpr int NPASS = LOGK % LB == 0 ? LOGK / LB : LOGK / LB + 1;
   static constexpr int LDS_ELEMS = K * W;
   static_assert(K >= 32 && K <= 4096 && (K & (K - 1)) == 0, "K");
   static_assert(NPASS >= 2, "at least two passes");
@@ -168,14 +205,14 @@ struct FftPanel {
     if constexpr (NPASS >= 4) {
 #pragma unroll 1
       for (int p = 1; p < NPASS - 1; ++p) {
-        pass<8, false, false>(lds, tw, ns, load, store);
-        ns *= 8;
+        pass<RB, false, false>(lds, tw, ns, load, store);
+        ns *= RB;
       }
     } else if constexpr (NPASS == 3) {
-      pass<8, false, false>(lds, tw, ns, load, store);
-      ns *= 8;
+      pass<RB, false, false>(lds, tw, ns, load, store);
+      ns *= RB;
     }
-    pass<8, false, true>(lds, tw, ns, load, store);
+    pass<RB, false, true>(lds, tw, ns, load, store);
   }
 };
 
