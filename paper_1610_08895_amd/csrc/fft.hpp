@@ -155,11 +155,35 @@ struct FftPanel {
         if (!FIRST) {
           const int k = j & (ns - 1);
           const int step = k * (K / (ns * R));
+          if constexpr (R == 16) {
+            // w^r from the loaded w, w^2, w^4, w^8 (at most three roundings each), which
+            // replaces eleven of the fifteen LDS reads of the table
+            float2 w[16];
+            w[1] = tw[step];
+            w[2] = tw[2 * step];
+            w[4] = tw[4 * step];
+            w[8] = tw[8 * step];
+            if (DIR > 0) {
+              w[1].y = -w[1].y;
+              w[2].y = -w[2].y;
+              w[4].y = -w[4].y;
+              w[8].y = -w[8].y;
+            }
+            w[3] = cmul(w[1], w[2]);
+            w[5] = cmul(w[1], w[4]);
+            w[6] = cmul(w[2], w[4]);
+            w[7] = cmul(w[3], w[4]);
 #pragma unroll
-          for (int r = 1; r < R; ++r) {
-            float2 t = tw[r * step];
-            if (DIR > 0) t.y = -t.y;
-            a[p][r] = cmul(a[p][r], t);
+            for (int r = 1; r < 8; ++r) w[8 + r] = cmul(w[r], w[8]);
+#pragma unroll
+            for (int r = 1; r < R; ++r) a[p][r] = cmul(a[p][r], w[r]);
+          } else {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+              float2 t = tw[r * step];
+              if (DIR > 0) t.y = -t.y;
+              a[p][r] = cmul(a[p][r], t);
+            }
           }
         }
         dft<R, DIR>(a[p]);
