@@ -177,6 +177,22 @@ struct FftPanel {
             for (int r = 1; r < 8; ++r) w[8 + r] = cmul(w[r], w[8]);
 #pragma unroll
             for (int r = 1; r < R; ++r) a[p][r] = cmul(a[p][r], w[r]);
+          } else if constexpr (R == 8) {  // likewise from w, w^2, w^4
+            float2 w[8];
+            w[1] = tw[step];
+            w[2] = tw[2 * step];
+            w[4] = tw[4 * step];
+            if (DIR > 0) {
+              w[1].y = -w[1].y;
+              w[2].y = -w[2].y;
+              w[4].y = -w[4].y;
+            }
+            w[3] = cmul(w[1], w[2]);
+            w[5] = cmul(w[1], w[4]);
+            w[6] = cmul(w[2], w[4]);
+            w[7] = cmul(w[3], w[4]);
+#pragma unroll
+            for (int r = 1; r < R; ++r) a[p][r] = cmul(a[p][r], w[r]);
           } else {
 #pragma unroll
             for (int r = 1; r < R; ++r) {
