@@ -6,7 +6,7 @@
 //     phase at the image edge);
 //   * inside each block, visibilities are sorted by (grid tile, cell) and cut into work
 //     items of at most `bin` visibilities of one tile;
-//   * Kaiser-Bessel weights are fitted per tap by degree-9 polynomials (Chebyshev
+//   * Kaiser-Bessel weights are fitted per tap by degree-7 polynomials (Chebyshev
 //     interpolation of the kernel evaluated with an I0 power series);
 //   * twiddles exp(-2 pi i k / K) and the pre-compensation S = 1/phi_hat(l/K) are
 //     evaluated in FP64 and rounded to FP32.
@@ -130,7 +130,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   // Kaiser-Bessel polynomials
   std::vector<double> mono;
   kb_fit_taps(J, p.beta, 2 * KB_HALF_DEG + 1, mono, &p.poly_err);
-  if (!(p.poly_err < 1e-8)) return fail(RI_EINVAL, "kernel polynomial fit error %.3g too large (beta %.3f)", p.poly_err, p.beta);
+  if (!(p.poly_err < 2e-7)) return fail(RI_EINVAL, "kernel polynomial fit error %.3g too large (beta %.3f)", p.poly_err, p.beta);
   for (int j = 0; j < KB_J / 2; ++j)
     for (int k = 0; k <= KB_HALF_DEG; ++k) {
       p.poly.e[j][k] = float(mono[size_t(j) * (2 * KB_HALF_DEG + 2) + 2 * k]);
