@@ -237,10 +237,11 @@ enum { GR_APPLY = 0, GR_PROJECT = 1 };
 // by a power of two 2^E chosen from the item's sum of |Re| + |Im|, which bounds any cell's
 // sum, so each field stays below 2^30 in magnitude.  A contribution (re, im) is added as
 // the 64-bit word re + (im + c) 2^32 with re taken modulo 2^32 in the low half, where c is
-// -1 for the rows whose Re factor is negative and 0 otherwise (folded into the rounding
-// of im): the word then equals re + im' 2^32 exactly with im' = im + c + [re < 0], and since
-// the kernel weights are positive, re < 0 exactly when the row's factor is negative except
-// for products that round to zero, so im' differs from im by at most one unit.  Decoding
+// -1 for the rows whose Re factor has its sign bit set and 0 otherwise (folded into the
+// rounding of im as a copysign of its 0.5 offset): the word then equals re + im' 2^32 exactly
+// with im' = im + c + [re < 0], and since the kernel weights are positive, re < 0 exactly
+// when the row's factor is negative except for products that round to zero, so im' differs
+// from im by at most one unit.  Decoding
 // subtracts the sign-extended low field.  Rounding (to nearest, halves up) is at most
 // 2^-E-1 per contribution for Re and 2^-E-1 + 2^-E for Im.
 //
@@ -405,7 +406,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
 #pragma unroll
             for (int r = 0; r < KB_J; ++r) {
               const float tr = wy[r] * vr, ti = wy[r] * vi;
-              const float ci = tr < 0.f ? -0.5f : 0.5f;  // Im rounding offset with the borrow c
+              const float ci = copysignf(0.5f, tr);  // Im rounding offset with the borrow c
 #pragma unroll
               for (int b = 0; b < KB_J; ++b) {
                 const int ir = int(floorf(fmaf(wx[b], tr, 0.5f))), ii = int(floorf(fmaf(wx[b], ti, ci)));
