@@ -81,11 +81,40 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
-// Wavefront-level FP64 sum (64 lanes), result valid in every lane.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+// Lane moves of the sums below, as DPP modifiers of a VALU move (no LDS traffic).  Rows
+// of 16 lanes outside ROWS keep 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float lane_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double lane_move(double v) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, ROWS, 0xf, false);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+__device__ __forceinline__ float lane63(float v) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63)); }
+__device__ __forceinline__ double lane63(double v) {
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  const unsigned lo = __builtin_amdgcn_readlane(int(b), 63), hi = __builtin_amdgcn_readlane(int(b >> 32), 63);
+  return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wavefront whose lanes are all active; the result is returned
+// to every lane.  Pairs and quads through quad permutes, eights and rows of 16 through the
+// half-row and row mirrors, then row 15's sum is broadcast into rows 1 and 3 and lane 31's
+// into rows 2 and 3, which leaves the total in lane 63.  The order of the additions is
+// fixed, so the sum is deterministic.
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+  v += lane_move<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += lane_move<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += lane_move<0x141, 0xf>(v);  // row_half_mirror
+  v += lane_move<0x140, 0xf>(v);  // row_mirror
+  v += lane_move<0x142, 0xa>(v);  // row_bcast:15
+  v += lane_move<0x143, 0xc>(v);  // row_bcast:31
+  return lane63(v);
 }
 
 }  // namespace ri

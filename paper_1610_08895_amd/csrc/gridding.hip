@@ -325,7 +325,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
         babs += fabsf(val[k].x) + fabsf(val[k].y);
       }
     }
-    for (int off = 32; off > 0; off >>= 1) babs += __shfl_xor(babs, off, 64);
+    babs = wave_sum(babs);
     if (lane == 0) red_b[buf][wv] = babs;
   };
   // this thread's region cells
