@@ -75,6 +75,19 @@ struct Pitch {
   static constexpr int TP = T + 9;
 };
 
+// Position of region cell (ly, lx), outside the tile interior [R0, R0 + T)^2, in the tile's
+// halo ring, which is stored compactly: the full-width rows above the interior, then those
+// below it, then for each interior row its R0 cells on the left and its TW - T - R0 cells on
+// the right.  Readers of the left and right edges then take whole cache lines.
+template <int T>
+__device__ __forceinline__ int ring_index(int ly, int lx) {
+  constexpr int TW = Pitch<T>::TW, R0 = KB_J / 2 - 1;
+  if (ly < R0) return ly * TW + lx;
+  if (ly >= R0 + T) return (ly - T) * TW + lx;
+  return (TW - T) * TW + (ly - R0) * (TW - T) + (lx < R0 ? lx : lx - T);
+}
+static_assert((Pitch<32>::TW - 32) * Pitch<32>::TW + 32 * (Pitch<32>::TW - 32) == ring_cells(32), "ring layout");
+
 // Degridding over units {tile, first, end} of the unit-ordered items (items of one tile,
 // several blocks): the tile and its reach are staged once per unit, then the waves go
 // through the unit's items without synchronising.  Each thread loads all of its (at most
@@ -430,10 +443,13 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
     }
     const int sp = unit_patch != nullptr ? unit_patch[u] : -1;
     if (pend) fold(buf ^ 1, pbox, pinv);
-    float2* patch = sp >= 0 ? spatch + size_t(sp) * TW * TW : halo + size_t(un.x) * TW * TW;
+    float2* patch = sp >= 0 ? spatch + size_t(sp) * TW * TW : halo + size_t(un.x) * ring_cells(T);
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      const int c = threadIdx.x + j * GGT;
+      // the cell's coordinates and addresses are recomputed for every unit (an empty asm
+      // hides that they do not change): keeping them across the unit loop costs registers
+      int c = threadIdx.x + j * GGT;
+      asm volatile("" : "+v"(c));
       if (c >= TW * TW) continue;
       const int ly = c / TW, lx = c - (c / TW) * TW;
       const float2 a = acc[j];
@@ -446,8 +462,10 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
           const float2 old = *g;
           *g = make_float2(old.x + a.x, old.y + a.y);
         }
+      } else if (sp < 0) {
+        patch[ring_index<T>(ly, lx)] = a;  // the ring
       } else {
-        patch[c] = a;  // the ring, or a further slice's whole region
+        patch[c] = a;  // a further slice's whole region
       }
     }
   }
@@ -505,7 +523,7 @@ __global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, flo
         if (ly < 0 || ly >= TW || lx < 0 || lx >= TW) continue;
         const int nt = ((ty + dy + tpa) & (tpa - 1)) * tpa + ((tx + dx + tpa) & (tpa - 1));
         if (dy != 0 || dx != 0) {
-          float2* hp = &halo[size_t(nt) * TW * TW + ly * TW + lx];
+          float2* hp = &halo[size_t(nt) * ring_cells(T) + ring_index<T>(ly, lx)];
           const float2 h = *hp;
           acc.x += h.x;
           acc.y += h.y;
@@ -591,7 +609,7 @@ int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const
                 float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
                 bool with_halo = true, bool fresh = false) {
   if (!sliced && p.halo_dirty) {  // per-block gridding needs all-zero patches to start from
-    RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * (T + 8) * (T + 8), s));
+    RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * ring_cells(T), s));
     p.halo_dirty = false;
   }
   if (fresh && p.n_empty > 0) {

@@ -343,7 +343,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   }
   RI_TRY(dev_alloc(&p.item_part, 2 * size_t(PART_WAVES) * items.size()));
   RI_TRY(dev_alloc(&p.block_tmp, 2 * size_t(d)));
-  RI_TRY(dev_alloc(&p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8)));
+  RI_TRY(dev_alloc(&p.halo, size_t(p.n_tiles) * ring_cells(p.tile)));
   if (p.n_empty > 0) {
     RI_TRY(dev_alloc(&p.empty_tiles, empty_tiles.size()));
     RI_HIP(hipMemcpyAsync(p.empty_tiles, empty_tiles.data(), empty_tiles.size() * sizeof(int), hipMemcpyHostToDevice,
@@ -369,7 +369,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
     RI_HIP(hipMemcpyAsync(p.tile_sp, tile_sp.data(), tile_sp.size() * sizeof(int), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.scale, sc.data(), n * sizeof(float), hipMemcpyHostToDevice, s));
   // tiles without visibilities keep an all-zero halo patch forever
-  RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * (p.tile + 8) * (p.tile + 8), s));
+  RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * ring_cells(p.tile), s));
   RI_HIP(hipStreamSynchronize(s));
   return RI_OK;
 }

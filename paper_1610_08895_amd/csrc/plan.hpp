@@ -31,6 +31,9 @@ using Item = int4;
 constexpr int MAX_BIN = 1024;    // largest `bin` (the gridding kernel stages an item's values in LDS)
 constexpr int DUNIT_VIS = 2048;  // visibilities per degridding unit (several items of one tile)
 constexpr int PART_WAVES = 4;    // FP64 norm partials per work item (one per wavefront)
+// Cells of a tile's halo ring: its (tile + 8)^2 region (the tile and the kernel's reach)
+// less the tile itself.
+constexpr int ring_cells(int tile) { return (tile + 8) * (tile + 8) - tile * tile; }
 
 struct Plan {
   int n = 0, K = 0, J = KB_J, d = 0;
@@ -82,7 +85,7 @@ struct Plan {
   int4* dunits = nullptr;       // degridding units, densest first; ranges into titems
   double* item_part = nullptr;  // 2 * PART_WAVES * n_items partial sums of the block norms
   double* block_tmp = nullptr;  // 2 * d
-  float2* halo = nullptr;       // n_tiles * (tile + 8)^2 halo patches of the gridding
+  float2* halo = nullptr;       // n_tiles * ring_cells(tile) halo rings of the gridding
   int n_empty = 0;
   int* empty_tiles = nullptr;   // n_empty tiles without visibilities
   // The batched gridding rewrites the whole ring of every tile with visibilities in each
