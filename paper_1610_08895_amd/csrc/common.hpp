@@ -103,9 +103,9 @@ __device__ __forceinline__ double lane63(double v) {
 
 // Sum over the 64 lanes of a wavefront whose lanes are all active; the result is returned
 // to every lane.  Pairs and quads through quad permutes, eights and rows of 16 through the
-// half-row and row mirrors, then row 15's sum is broadcast into rows 1 and 3 and lane 31's
-// into rows 2 and 3, which leaves the total in lane 63.  The order of the additions is
-// fixed, so the sum is deterministic.
+// half-row and row mirrors; then lane 15 of rows 0 and 2 (their row sums) is added into
+// rows 1 and 3, and lane 31 (rows 0 + 1) into rows 2 and 3, which leaves the total in lane
+// 63.  The order of the additions is fixed, so the sum is deterministic.
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
   v += lane_move<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
