@@ -221,6 +221,16 @@ def main():
     phia_ms = ev[1].elapsed_time(ev[2]) / args.op_reps
     log(f"Phi {phi_ms:.4f} ms ({w.M / phi_ms / 1e6:.1f} Gvis/s), Phi^dagger {phia_ms:.4f} ms "
         f"({w.M / phia_ms / 1e6:.1f} Gvis/s)")
+    # ---- Eq. 13 at x for every block (the adaptive schedule's exact refresh) ----
+    rs = torch.empty(plan.d, 2, dtype=torch.float64, device="cuda")
+    sol.pd.residual(rs)
+    ev[0].record()
+    for _ in range(args.op_reps):
+        sol.pd.residual(rs)
+    ev[1].record()
+    torch.cuda.synchronize()
+    resid_ms = ev[0].elapsed_time(ev[1]) / args.op_reps
+    log(f"Eq. 13 refresh (all blocks at x) {resid_ms:.4f} ms")
 
     # ---- CPU oracle baseline: one iteration of Algorithm 1 on the same workload ----
     cpu = None
@@ -266,6 +276,7 @@ def main():
                    "kernel": "Kaiser-Bessel 8x8, 2x oversampling", "sara": "Dirac + db1..db8, 4 levels"},
         "phi_gvis_s": round(w.M / phi_ms / 1e6, 2),
         "phi_adj_gvis_s": round(w.M / phia_ms / 1e6, 2),
+        "eq13_refresh_ms": round(resid_ms, 4),
         "plain_iters_s": round(1e3 / plain_ms, 3) if plain_ms else None,
         "speedup_vs_plain": round(plain_ms / ms_per_step, 3) if plain_ms else None,
         "stage_algorithmic_bytes": sb,

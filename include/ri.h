@@ -189,6 +189,15 @@ int ri_pd_step_plain(ri_pd pd, const uint8_t* mask_host, double* stats, hipStrea
  * the accumulated rounding.  Enqueue-only (graph-capturable). */
 int ri_pd_refresh(ri_pd pd, hipStream_t stream);
 
+/* Sec. IV, Eq. 13 at the current primal iterate x (all blocks, active or not): a forward
+ * FFT of x and one residual pass over all visibilities.  out: device d x 2 float64;
+ * out[2i+1] = ||Phi_i x - y_i||^2 (FP64, fixed summation order), out[2i] =
+ * ||v_i + Phi_i x - y_i||^2.  The solver state is not changed (the residual goes to scratch
+ * that the first call allocates, M complex values); the plan's FFT grid is overwritten,
+ * which the next step recomputes anyway.  Enqueue-only after the first call.
+ * Errors: RI_EINVAL (NULL pd or out), RI_ENOMEM, RI_EHIP. */
+int ri_pd_residual(ri_pd pd, double* out, hipStream_t stream);
+
 /* Stages of one iteration, for per-stage timing (each stage is one kernel launch in the
  * batched step; the plain step times all per-block launches of a stage together). */
 enum {

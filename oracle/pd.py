@@ -19,7 +19,9 @@ Per active block the iteration also reports ||v_i + G_i b_i - y_i|| (the norm th
 projection uses) and ||G_i b_i - y_i|| = ||Phi_i x~ - y_i||.  The second one drives
 Eq. 13 in ``run_adaptive``: c_i is refreshed from it when block i is active and kept
 otherwise, and at the start is computed from x = 0 (the paper leaves open when c_i is
-evaluated; Eq. 13 itself asks for Phi_i x at the current iterate).
+evaluated; Eq. 13 itself asks for Phi_i x at the current iterate).  With refresh_every = K,
+every K iterations c_i is also recomputed for all blocks exactly as Eq. 13 states, from
+||Phi_i x - y_i|| at the current primal iterate x (``residual_norms``).
 
 Pins: invariants every iteration (x >= 0, |s| <= alpha, v_i = 0 whenever the block's
 residual is inside its ball), the x = 0 special case, mask-all-ones equal to the
@@ -135,9 +137,18 @@ def run(meas, sara, y, eps, prm: Params, masks, x_true=None, state=None, callbac
     return st, hist
 
 
-def run_adaptive(meas, sara, y, eps, prm: Params, uniforms, n_nodes, p_min, p_max, x_true=None):
+def residual_norms(meas, x, y_blocks):
+    """||Phi_i x - y_i|| for every block i (the residual of Eq. 13 at x)."""
+    b_full = meas.F(meas.Z(x))
+    return np.array([np.linalg.norm(meas.Gi(i, meas.Mi(i, b_full)) - y_blocks[i]) for i in range(meas.d)])
+
+
+def run_adaptive(meas, sara, y, eps, prm: Params, uniforms, n_nodes, p_min, p_max, x_true=None,
+                 refresh_every=0):
     """Algorithm 1 with Eq. 14 probabilities; block i is active at iteration t iff
-    uniforms[t, i] < p_i^(t).  Returns (state, history, masks, probabilities)."""
+    uniforms[t, i] < p_i^(t).  With refresh_every = K > 0, before iteration t (t > 0,
+    t a multiple of K) every c_i is recomputed from Eq. 13 at the current x.  Returns
+    (state, history, masks, probabilities)."""
     from .metrics import snr
 
     yb = split_blocks(meas, y)
@@ -145,7 +156,9 @@ def run_adaptive(meas, sara, y, eps, prm: Params, uniforms, n_nodes, p_min, p_ma
     # c_i at x = 0: ||y_i|| against eps_i
     c = residual_energy([np.linalg.norm(b) for b in yb], eps)
     masks, probs, hist = [], [], []
-    for u in np.asarray(uniforms):
+    for t, u in enumerate(np.asarray(uniforms)):
+        if refresh_every and t > 0 and t % refresh_every == 0:
+            c = residual_energy(residual_norms(meas, st.x, yb), eps)
         p, _ = adaptive_probabilities(c, n_nodes, p_min, p_max)
         mask = u < p
         stats = iteration(meas, sara, yb, eps, prm, st, mask)

@@ -57,6 +57,7 @@ SIGNATURES = {
     "ri_pd_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ri_pd_step_plain": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "ri_pd_refresh": (c_int, [c_void_p, c_void_p]),
+    "ri_pd_residual": (c_int, [c_void_p, c_void_p, c_void_p]),
     "ri_pd_timing": (c_int, [c_void_p, c_int]),
     "ri_pd_stage_times": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
     "ri_pd_get": (c_int, [c_void_p, c_int, c_void_p, c_size_t, c_void_p]),

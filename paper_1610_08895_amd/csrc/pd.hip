@@ -50,6 +50,8 @@ struct ri_pd_s {
   float2* vj_phiz = nullptr;  // M: Phi zbar
   double* vj_part = nullptr;  // dot-product and per-block partials
   double* vj_coef = nullptr;  // 2 d
+  // residual at x of ri_pd_residual (M complex), allocated on its first call
+  float2* res_e = nullptr;
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // optional per-stage timing: an event pair around each stage, on the stage's stream
@@ -126,6 +128,7 @@ void destroy_pd(ri_pd_s* P) {
   dev_free(P->vj_phiz);
   dev_free(P->vj_part);
   dev_free(P->vj_coef);
+  dev_free(P->res_e);
   if (P->ev_fork) (void)hipEventDestroy(P->ev_fork);
   if (P->ev_join) (void)hipEventDestroy(P->ev_join);
   if (P->side) (void)hipStreamDestroy(P->side);
@@ -361,6 +364,19 @@ int ri_pd_stage_times(ri_pd P, double* total_ms, int* launches, int n) {
 int ri_pd_refresh(ri_pd P, hipStream_t stream) {
   if (!P) return fail(RI_EINVAL, "pd is NULL");
   return ri::refresh_sum(P, stream);
+}
+
+int ri_pd_residual(ri_pd P, double* out, hipStream_t stream) {
+  if (!P || !out) return fail(RI_EINVAL, "pd and out must not be NULL");
+  const ri::Plan& p = *P->plan;
+  if (!P->res_e) RI_TRY(ri::dev_alloc(&P->res_e, size_t(p.M)));
+  // Eq. 13 needs Phi_i x - y_i at the primal iterate x, for every block: the forward FFT of
+  // x into the plan's grid (each step recomputes that grid from x~ first), the residual
+  // pass over all items with the norms in fixed order, into scratch so that the step's
+  // state (v, the running sum, RI_PD_E) is untouched
+  RI_TRY(ri::fft_forward(p, P->x, p.grid, stream));
+  RI_TRY(ri::degrid_residual(p, p.grid, P->y, P->v, P->res_e, nullptr, stream));
+  return ri::block_stats(p, nullptr, P->stats, out, stream);
 }
 
 int ri_pd_get(ri_pd P, int which, void* buf, size_t bytes, hipStream_t stream) {

@@ -199,6 +199,14 @@ class PD:
     def refresh(self):
         L.check(L.load().ri_pd_refresh(self._h, _stream()))
 
+    def residual(self, out=None):
+        """(d, 2) FP64 device tensor; column 1 holds ||Phi_i x - y_i||^2 at the current x for
+        every block (ri_pd_residual), column 0 ||v_i + Phi_i x - y_i||^2."""
+        if out is None:
+            out = torch.empty(self.plan.d, 2, dtype=torch.float64, device="cuda")
+        L.check(L.load().ri_pd_residual(self._h, _dev(out, torch.float64, (self.plan.d, 2), "out"), _stream()))
+        return out
+
     def step_vjp(self, mask, x_new, s_new, v_new, v_old, e, stats, xbar, xtbar, sbar, vbar, pgrad):
         """Reverse sweep of one step (ri_pd_step_vjp): the adjoints xbar, xtbar, sbar, vbar
         are updated in place from after the step to before it; pgrad (2 FP64) accumulates

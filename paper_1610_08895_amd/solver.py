@@ -17,13 +17,23 @@ from .ops import PD, Plan, Sara, probabilities, residual_energy
 
 @dataclasses.dataclass
 class Schedule:
-    """How blocks are drawn: kind "uniform" (all p_i = p) or "adaptive" (Eq. 14)."""
+    """How blocks are drawn (Sec. III-B, IV).
+
+    kind "uniform": every p_i = p.  kind "fixed": the per-block probabilities p_vec (for
+    instance 1 for the low-frequency blocks and 0 for the others).  kind "adaptive": Eq. 14
+    from the c_i of Eq. 13 with sum_i p_i = n_nodes, p_min <= p_i <= p_max; c_i starts at
+    x = 0, is updated after each step for the blocks that were active (from that step's
+    residual, taken at x~), and, with refresh_every = K > 0, is recomputed for every block
+    at the primal iterate x every K iterations (one forward FFT and residual pass).
+    """
 
     kind: str = "uniform"
     p: float = 1.0
     n_nodes: float = 0.0
     p_min: float = 0.05
     p_max: float = 0.5
+    p_vec: tuple = ()
+    refresh_every: int = 0
 
 
 def step_sizes(psi_norm, phi_norm, tau=0.49):
@@ -45,6 +55,11 @@ class Solver:
     def initial_energy(self):
         """Eq. 13 at x = 0 (the residual is the data itself)."""
         sq = self.plan.block_sumsq(self.y_plan).cpu().numpy()
+        return residual_energy(np.sqrt(sq), self.eps)
+
+    def energy(self):
+        """Eq. 13 at the current primal iterate x, for every block."""
+        sq = self.pd.residual().cpu().numpy()[:, 1]
         return residual_energy(np.sqrt(sq), self.eps)
 
     def capture(self):
@@ -78,25 +93,38 @@ class Solver:
     def run(self, iterations, schedule: Schedule = Schedule(), uniforms=None, masks=None, refresh=64,
             x_true=None, snr_every=0, graph=False, plain=False, callback=None):
         """Run `iterations` steps.  Masks come from `masks` (replayed), else from
-        `uniforms` (T x d) against the schedule's probabilities.  Returns a history dict."""
+        `uniforms` (T x d) against the schedule's probabilities; with masks replayed, an
+        adaptive schedule's probabilities are still computed and logged.  `refresh` rebuilds
+        the running sum of G_i^dagger v_i every that many steps.  Returns a history dict."""
         d = self.plan.d
-        c = self.initial_energy() if schedule.kind == "adaptive" else None
+        adaptive = schedule.kind == "adaptive"
+        c = self.initial_energy() if adaptive else None
+        if schedule.kind == "fixed":
+            p_fixed = np.asarray(schedule.p_vec, dtype=np.float64)
+            if p_fixed.shape != (d,) or np.any(p_fixed < 0) or np.any(p_fixed > 1):
+                raise ValueError("p_vec must hold d probabilities in [0, 1]")
+        elif schedule.kind not in ("uniform", "adaptive"):
+            raise ValueError(f"unknown schedule kind {schedule.kind!r}")
         hist = {"masks": [], "p": [], "snr": []}
         for t in range(iterations):
+            if adaptive and schedule.refresh_every and t > 0 and t % schedule.refresh_every == 0:
+                c = self.energy()
+            if adaptive:
+                p, _ = probabilities(c, schedule.n_nodes, schedule.p_min, schedule.p_max)
+            elif schedule.kind == "fixed":
+                p = p_fixed
+            else:
+                p = np.full(d, schedule.p)
             if masks is not None:
                 mask = np.asarray(masks[t], dtype=np.uint8)
-                p = None
             else:
-                if schedule.kind == "adaptive":
-                    p, _ = probabilities(c, schedule.n_nodes, schedule.p_min, schedule.p_max)
-                else:
-                    p = np.full(d, schedule.p)
                 mask = (uniforms[t] < p).astype(np.uint8) if uniforms is not None else np.ones(d, np.uint8)
             self.step(mask, graph=graph, plain=plain)
-            if schedule.kind == "adaptive" and masks is None:
+            if adaptive:
                 st = self.stats_dev.cpu().numpy()
                 act = np.flatnonzero(mask)
-                c[act] = residual_energy(np.sqrt(st[act, 1]), self.eps[act])
+                if act.size:  # an empty active set leaves every c_i as it was
+                    c[act] = residual_energy(np.sqrt(st[act, 1]), self.eps[act])
             if refresh and (t + 1) % refresh == 0:
                 self.pd.refresh()
             hist["masks"].append(mask)

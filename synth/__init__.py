@@ -61,6 +61,10 @@ WORKLOADS = {
         Workload("n1024_m4m_d64", 1024, 200, 1000, 1 << 22, 64, "lognormal", 20.0, 0.0, 200,
                  (("p1", "uniform", {"p": 1.0}),
                   ("adaptive16", "adaptive", {"n_nodes": 16.0, "p_min": 0.05, "p_max": 0.5}))),
+        # Sec. V's adaptive-probability experiment: 256^2, M = 5N, 16 equal blocks, 20 dB
+        Workload("n256_m320k_d16", 256, 5, 10, 5 * 256 * 256, 16, "equal", 20.0, 0.0, 600,
+                 (("p1", "uniform", {"p": 1.0}),
+                  ("adaptive4", "adaptive", {"n_nodes": 4.0, "p_min": 0.05, "p_max": 0.5}))),
         Workload("n512_m1m_d32", 512, 5, 10, 1 << 20, 32, "equal", 20.0, 0.0, 20,
                  (("p1", "uniform", {"p": 1.0}),)),
         Workload("n2048_m16m_d128", 2048, 200, 1000, 1 << 24, 128, "lognormal", 20.0, 0.1, 1000,

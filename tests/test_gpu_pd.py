@@ -196,3 +196,75 @@ def test_graph_replay_matches_eager(R):
         torch.cuda.synchronize()
         assert rel_l2(graph.x(), eager.x()) < 1e-5, t
         assert torch.allclose(graph.stats_dev.nan_to_num(-1), eager.stats_dev.nan_to_num(-1), rtol=1e-5)
+
+
+def test_pd_residual_matches_oracle(R):
+    """ri_pd_residual: ||Phi_i x - y_i||^2 and ||v_i + Phi_i x - y_i||^2 for every block at a
+    seeded x and v; at x = 0 the first is the data's own per-block energy."""
+    S = _setup(R, n=64, M=12000, d=8, scheme="annuli", seed=13, isnr=20.0)
+    pdg = _pd(R, S)
+    meas = S["meas"]
+    yb = opd.split_blocks(meas, S["y"])
+    rng = np.random.default_rng(14)
+    x = np.abs(synth.sky(64, 5, 10, rng))
+    v_user = 0.01 * (rng.standard_normal(meas.M) + 1j * rng.standard_normal(meas.M))
+    pdg.set(0, torch.tensor(x, dtype=torch.float32, device="cuda"))
+    pdg.set(3, torch.tensor(to_plan(v_user, S["order"]), dtype=torch.complex64, device="cuda"))
+    out = pdg.residual().cpu().numpy()
+    xf = x.astype(np.float32).astype(np.float64)
+    ref1 = opd.residual_norms(meas, xf, yb) ** 2
+    b_full = meas.F(meas.Z(xf))
+    vb = opd.split_blocks(meas, v_user.astype(np.complex64))
+    ref0 = np.array([np.linalg.norm(vb[i] + meas.Gi(i, meas.Mi(i, b_full)) - yb[i]) ** 2 for i in range(meas.d)])
+    assert np.allclose(out[:, 1], ref1, rtol=1e-4)
+    assert np.allclose(out[:, 0], ref0, rtol=1e-4)
+    pdg.set(0, torch.zeros(64, 64, dtype=torch.float32, device="cuda"))
+    out0 = pdg.residual().cpu().numpy()
+    assert np.allclose(out0[:, 1], S["plan"].block_sumsq(S["y_plan"]).cpu().numpy(), rtol=1e-12)
+
+
+def test_pd_residual_leaves_the_state(R):
+    """A residual evaluation between two steps changes nothing the next step computes."""
+    S = _setup(R, n=64, M=8192, d=4, seed=15)
+    a, b = _pd(R, S), _pd(R, S)
+    mask = torch.tensor([1, 0, 1, 1], dtype=torch.uint8, device="cuda")
+    for pdg in (a, b):
+        pdg.step()
+        pdg.step(mask)
+    e_before = a.get(5).clone()
+    a.residual()
+    assert torch.equal(a.get(5), e_before)
+    for pdg in (a, b):
+        pdg.step(mask)
+    for which in (0, 1, 2, 3, 5):
+        assert torch.equal(a.get(which), b.get(which)), which
+
+
+def test_adaptive_refresh_matches_oracle(R):
+    """Eq. 14 with c_i refreshed from Eq. 13 at x every K iterations: the GPU solver, driven
+    with the oracle's mask log, computes the oracle's probabilities at every iteration."""
+    from paper_1610_08895_amd.solver import Schedule, Solver
+
+    S = _setup(R, n=64, M=12000, d=8, scheme="annuli", seed=8, isnr=20.0)
+    T, K = 40, 8
+    u = synth.activity_uniforms(T, S["plan"].d, 98)
+    st, hist, masks, probs = opd.run_adaptive(S["meas"], S["osara"], S["y"], S["eps"], S["prm"], u, n_nodes=3.0,
+                                              p_min=0.05, p_max=0.8, x_true=S["x"], refresh_every=K)
+    sol = Solver(S["plan"], S["sara"], S["y_plan"], S["eps"], 3.0, S["phin"])
+    h = sol.run(T, Schedule("adaptive", n_nodes=3.0, p_min=0.05, p_max=0.8, refresh_every=K), masks=masks,
+                refresh=16)
+    gp = np.array(h["p"])
+    assert np.allclose(gp, probs, rtol=0, atol=2e-3)
+    assert abs(snr(S["x"], sol.x()) - hist[-1]["snr"]) <= 0.05
+
+
+def test_adaptive_run_survives_an_empty_active_set(R):
+    """An iteration with no active block leaves every c_i unchanged (Eq. 13 has nothing new)."""
+    from paper_1610_08895_amd.solver import Schedule, Solver
+
+    S = _setup(R, n=64, M=8192, d=4, seed=16)
+    sol = Solver(S["plan"], S["sara"], S["y_plan"], S["eps"], 3.0, S["phin"])
+    masks = np.zeros((3, 4), np.uint8)
+    masks[0] = 1
+    h = sol.run(3, Schedule("adaptive", n_nodes=2.0, p_min=0.1, p_max=0.9), masks=masks)
+    assert np.array_equal(h["p"][1], h["p"][2])

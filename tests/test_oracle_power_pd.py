@@ -129,3 +129,48 @@ def test_small_workload_trends():
     assert s[-1] > s[5] > 0.0
     assert s[-1] > 10.0
     assert np.max(metrics.ball_ratio(meas, st.x, y, eps)) < 3.0
+
+
+def test_residual_norms_against_the_direct_dft():
+    """Eq. 13's residual ||Phi_i x - y_i||: zero image gives ||y_i|| exactly; data made by
+    the direct non-uniform DFT plus a known per-block offset gives that offset's norm, to
+    the kernel's interpolation accuracy (Phi matches the direct DFT to < 1e-6)."""
+    from oracle.measurement import nudft
+
+    rng = np.random.default_rng(11)
+    n, M = 16, 300
+    uv = (rng.standard_normal((M, 2)) * np.pi / 4).clip(-3.1, 3.1).astype(np.float32)
+    meas = Measurement(uv, [0, 100, 220, M], (n, n))
+    x = np.abs(rng.standard_normal((n, n)))
+    delta = 0.1 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+    y = nudft(x, uv) + delta
+    yb = pd.split_blocks(meas, y)
+    r0 = pd.residual_norms(meas, np.zeros((n, n)), yb)
+    assert np.array_equal(r0, np.array([np.linalg.norm(b) for b in yb]))
+    r = pd.residual_norms(meas, x, yb)
+    ref = np.array([np.linalg.norm(b) for b in pd.split_blocks(meas, delta)])
+    scale = np.array([np.linalg.norm(b) for b in pd.split_blocks(meas, nudft(x, uv))])
+    assert np.all(np.abs(r - ref) <= 2e-6 * scale)
+
+
+def test_adaptive_refresh_takes_eq13_at_the_primal_iterate():
+    """With refresh_every = K, the probabilities of iteration K come from Eq. 13 evaluated
+    at x^(K) for every block: recomputed here from the direct DFT residual of the x reached
+    by replaying the same masks, then Eq. 14."""
+    from oracle.measurement import nudft
+    from oracle.probs import adaptive_probabilities, residual_energy
+
+    meas, sara, x_true, y, eps, prm = _tiny_problem(seed=12, n=8, M=60)
+    K, T = 3, 5
+    u = np.random.default_rng(5).random((T, meas.d))
+    st, _, masks, probs = pd.run_adaptive(meas, sara, y, eps, prm, u, n_nodes=1.2, p_min=0.3, p_max=1.0,
+                                          refresh_every=K)
+    st_k, _ = pd.run(meas, sara, y, eps, prm, masks[:K])
+    resid = y - nudft(st_k.x, meas.uv.astype(np.float32))
+    rn = np.array([np.linalg.norm(b) for b in pd.split_blocks(meas, resid)])
+    p_ref, _ = adaptive_probabilities(residual_energy(rn, eps), 1.2, 0.3, 1.0)
+    assert np.allclose(probs[K], p_ref, rtol=1e-4, atol=1e-6)
+    # without the refresh the probabilities of iteration K differ (inactive blocks' c_i stale
+    # or taken at x~ rather than x)
+    _, _, _, probs0 = pd.run_adaptive(meas, sara, y, eps, prm, u, n_nodes=1.2, p_min=0.3, p_max=1.0)
+    assert not np.allclose(probs0[K], p_ref, rtol=1e-4, atol=1e-6)
