@@ -268,3 +268,21 @@ def test_adaptive_run_survives_an_empty_active_set(R):
     masks[0] = 1
     h = sol.run(3, Schedule("adaptive", n_nodes=2.0, p_min=0.1, p_max=0.9), masks=masks)
     assert np.array_equal(h["p"][1], h["p"][2])
+
+
+def test_pd_residual_with_split_tiles_and_bad_arguments(R):
+    """The residual pass over all items also covers tiles split into slices; NULL arguments
+    are rejected with an error code, and a wrongly shaped output by the binding."""
+    from paper_1610_08895_amd import _lib as L
+
+    S = _setup(R, n=64, M=6000, d=5, scheme="lognormal", seed=17, slice_vis=150, bin=64)
+    pdg = _pd(R, S)
+    rng = np.random.default_rng(18)
+    x = np.abs(synth.sky(64, 5, 10, rng))
+    pdg.set(0, torch.tensor(x, dtype=torch.float32, device="cuda"))
+    out = pdg.residual().cpu().numpy()
+    ref = opd.residual_norms(S["meas"], x.astype(np.float32).astype(np.float64), opd.split_blocks(S["meas"], S["y"]))
+    assert np.allclose(out[:, 1], ref ** 2, rtol=1e-4)
+    assert L.load().ri_pd_residual(None, None, None) == -1
+    with pytest.raises(ValueError):
+        pdg.residual(torch.empty(5, 3, dtype=torch.float64, device="cuda"))
