@@ -103,6 +103,20 @@ __global__ __launch_bounds__(NT) void k_adj_rows(const float2* __restrict__ rows
   __shared__ float2 lds[K * W];
   __shared__ float2 twl[TwLds<K, W>::size];
   const int r0 = blockIdx.x * W;
+  // With one row per workgroup, K / 8 threads and a radix-8 last pass, thread t stores the
+  // outputs t + i K / 8, i < 8, of which i = 0, 1, 6, 7 are pixels: their x and s~ are
+  // loaded before the transform, so the update does not wait for them at the end.
+  constexpr bool PREF = UPD && W == 1 && NT == K / 8 && FftPanel<K, W, NT, +1, false>::RB == 8;
+  float xp[4] = {0.f, 0.f, 0.f, 0.f}, sp[4] = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (PREF) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = threadIdx.x + (i < 2 ? i : i + 4) * (K / 8);
+      const size_t o = size_t(r0) * n + pix_of(q, n, K);
+      xp[i] = u.x[o];
+      sp[i] = u.st[o];
+    }
+  }
   auto load = [&](int w, int k) -> float2 { return rows[size_t(r0 + w) * K + k]; };
   auto store = [&](int w, int q, float2 v) {
     const int c = pix_of(q, n, K);
@@ -111,8 +125,16 @@ __global__ __launch_bounds__(NT) void k_adj_rows(const float2* __restrict__ rows
       const size_t o = size_t(r) * n + c;
       const float g = v.x * (S[r] * S[c]);
       if (UPD) {
-        const float xo = u.x[o];
-        const float xn = fmaxf(0.f, xo - u.tau * (u.sigma * u.st[o] + u.varsigma * g));
+        float xo, so;
+        if constexpr (PREF) {
+          const int i = q < K / 8 ? 0 : (q < K / 4 ? 1 : (q < 7 * K / 8 ? 2 : 3));
+          xo = i == 0 ? xp[0] : (i == 1 ? xp[1] : (i == 2 ? xp[2] : xp[3]));
+          so = i == 0 ? sp[0] : (i == 1 ? sp[1] : (i == 2 ? sp[2] : sp[3]));
+        } else {
+          xo = u.x[o];
+          so = u.st[o];
+        }
+        const float xn = fmaxf(0.f, xo - u.tau * (u.sigma * so + u.varsigma * g));
         u.x[o] = xn;
         u.xt[o] = 2.f * xn - xo;
       } else {
