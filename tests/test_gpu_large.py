@@ -114,3 +114,25 @@ def test_data_fit_gradient_512(R):
     yt = torch.tensor(to_plan(y, plan.order()), dtype=torch.complex64, device="cuda")
     (0.5 * (AG.phi(plan, xt) - yt).abs().pow(2).sum()).backward()
     assert rel_l2(xt.grad.cpu().numpy(), og.data_fit_grad(meas, x0, y)) < 1e-5
+
+
+def test_pd_residual_full_size_sampled_blocks(R):
+    """Eq. 13's residual (ri_pd_residual) at the benchmark workload (1024^2, M = 2^22 in 64
+    log-normal blocks), in the launch configuration the benchmark uses: two blocks'
+    ||Phi_i x - y_i||^2 against the oracle evaluated on exactly those blocks' visibilities
+    (seeded sky and data)."""
+    w = synth.WORKLOADS["n1024_m4m_d64"]
+    inp = synth.make_inputs(w)
+    plan = R.Plan(w.n, inp.uv, inp.block_off)
+    rng = np.random.default_rng(34)
+    y_user = 20.0 * (rng.standard_normal(w.M) + 1j * rng.standard_normal(w.M))
+    y_plan = torch.tensor(to_plan(y_user, plan.order()), dtype=torch.complex64, device="cuda")
+    sara = R.Sara(w.n, 4)
+    pd = R.PD(plan, sara, y_plan, np.ones(w.d), 0.49, 1.0 / 9.0, 1.0 / 400.0 ** 2, 1e-3, 3.0, 400.0)
+    pd.set(0, torch.tensor(inp.x_true, dtype=torch.float32, device="cuda"))
+    out = pd.residual().cpu().numpy()
+    for i in (0, 37):
+        lo, hi = int(inp.block_off[i]), int(inp.block_off[i + 1])
+        meas = Measurement(inp.uv[lo:hi], np.array([0, hi - lo]), (w.n, w.n))
+        ref = np.linalg.norm(meas.phi(inp.x_true) - y_user[lo:hi].astype(np.complex64)) ** 2
+        assert out[i, 1] == pytest.approx(ref, rel=1e-5), i
