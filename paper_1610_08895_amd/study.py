@@ -9,9 +9,10 @@ with n = 4 nodes for d = 16 blocks): SNR against iterations for
 
 on the synthetic problem of workload n256_m320k_d16 (256 x 256 sky, M = 5N Gaussian u-v
 points cut into 16 equal radial blocks, 20 dB input SNR, radii at the chi-square 0.99
-quantile).  Every iteration runs in the library; the schedules differ only in the masks,
-which are drawn from seeded uniforms.  `python -m paper_1610_08895_amd.study` prints one
-JSON line per schedule.
+quantile).  With another workload the same ratios hold: n = d / 4 nodes, the lowest d / 4
+blocks for the low-frequency run.  Every iteration runs in the library; the schedules
+differ only in the masks, which are drawn from seeded uniforms.
+`python -m paper_1610_08895_amd.study [--workload NAME]` prints one JSON line per schedule.
 """
 import argparse
 import json
@@ -28,24 +29,25 @@ from .solver import Schedule, Solver, snr
 WORKLOAD = "n256_m320k_d16"
 
 
-def schedules(d, low=4, refresh_every=10):
-    """The compared schedules, by label."""
+def schedules(d, refresh_every=10):
+    """The compared schedules, by label: n = d / 4 nodes on average, as 4 of 16 in Sec. V."""
+    n = d / 4.0
     p_low = np.zeros(d)
-    p_low[:low] = 1.0  # blocks are radial and sorted by radius: the first ones are the low frequencies
+    p_low[: d // 4] = 1.0  # blocks are radial and sorted by radius: the first ones are the low frequencies
     return {
         "p=1": Schedule("uniform", p=1.0),
         "uniform 0.25": Schedule("uniform", p=0.25),
         "uniform 0.4": Schedule("uniform", p=0.4),
-        "adaptive pmin=0.05": Schedule("adaptive", n_nodes=4.0, p_min=0.05, p_max=0.5, refresh_every=refresh_every),
-        "adaptive pmin=0.1": Schedule("adaptive", n_nodes=4.0, p_min=0.1, p_max=0.5, refresh_every=refresh_every),
-        "adaptive pmin=0.2": Schedule("adaptive", n_nodes=4.0, p_min=0.2, p_max=0.5, refresh_every=refresh_every),
+        "adaptive pmin=0.05": Schedule("adaptive", n_nodes=n, p_min=0.05, p_max=0.5, refresh_every=refresh_every),
+        "adaptive pmin=0.1": Schedule("adaptive", n_nodes=n, p_min=0.1, p_max=0.5, refresh_every=refresh_every),
+        "adaptive pmin=0.2": Schedule("adaptive", n_nodes=n, p_min=0.2, p_max=0.5, refresh_every=refresh_every),
         "low frequencies only": Schedule("fixed", p_vec=tuple(p_low)),
     }
 
 
-def setup():
+def setup(workload=WORKLOAD):
     """Plan, dictionary, noisy data and operator norm of the study's workload."""
-    w = synth.WORKLOADS[WORKLOAD]
+    w = synth.WORKLOADS[workload]
     inp = synth.make_inputs(w)
     plan = Plan(w.n, inp.uv, inp.block_off)
     order = plan.order()
@@ -86,8 +88,8 @@ def iterations_to(traj, level):
     return None
 
 
-def run_study(iterations=600, seeds=(1,), labels=None, log=print):
-    S = setup()
+def run_study(iterations=600, seeds=(1,), labels=None, log=print, workload=WORKLOAD):
+    S = setup(workload)
     out = {}
     for label, sched in schedules(S["plan"].d).items():
         if labels is not None and label not in labels:
@@ -113,8 +115,10 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--iterations", type=int, default=600)
     ap.add_argument("--seeds", type=int, default=3, help="mask draws averaged per schedule")
+    ap.add_argument("--workload", default=WORKLOAD, choices=sorted(synth.WORKLOADS))
     args = ap.parse_args()
-    res = run_study(args.iterations, tuple(range(args.seeds)), log=lambda m: print(m, flush=True))
+    res = run_study(args.iterations, tuple(range(args.seeds)), log=lambda m: print(m, flush=True),
+                    workload=args.workload)
     for label, r in res.items():
         print(json.dumps({"schedule": label, **{k: v for k, v in r.items() if k != "snr"},
                           "snr_every_10": [round(v, 3) for _, v in r["snr"]]}), flush=True)
