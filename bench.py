@@ -9,12 +9,15 @@ from the chi-square 0.99 quantile.  All blocks active (p = 1).
 One step is one full iteration of Algorithm 1 (steps 3-18: F Z x~, degridding with the
 l2-ball projection and FP64 block norms, gridding of the dual change, F^dagger Z^dagger,
 Psi^dagger with the dual clip, Psi and the primal update), replayed from a captured HIP
-graph; inputs are resident in HBM before the timed region.  Also reported: Phi and
-Phi^dagger alone (Gvis/s), the plain per-block form of the step, per-stage HIP-event
-timings with the HBM roofline of the dominant kernel, and the FP64 CPU oracle timed on a
-bounded sample (one iteration) on the host.
+graph with the block selection on the device and the running-sum refresh every 64
+iterations; inputs are resident in HBM before the timed region; the tile and bin sizes are
+the autotuner's pick.  Also reported: Phi and Phi^dagger alone (Gvis/s and HBM fraction),
+the plain per-block form of the step, per-stage HIP-event timings with the HBM roofline of
+the dominant kernel, the method's randomised operating points (Eq. 14 with 16 of 64 blocks
+per iteration on average; 2048^2 with M = 2^24 at mean p = 0.25), and the FP64 CPU oracle
+timed on a bounded sample (one iteration) on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-extra]
 """
 import argparse
 import hashlib
@@ -50,15 +53,20 @@ def log(*a):
 def stage_bytes(n, M_active, wavelets=8):
     """Algorithmic HBM bytes of one launch of each stage (FP32; N = n^2 pixels, 4N grid cells).
 
-    Each operand is counted once at its size: complex grid 32N, half-transformed rows 16N,
-    images 4N, coefficients 4N per basis, visibilities 8 B per complex value."""
+    Each operand counts once at its size (complex grid 32N, half-transformed rows 16N, images
+    4N, coefficients 4N per basis, visibilities 8 B per complex value, packed coordinates 8 B
+    per visibility), following the minimal fused design of the method's per-iteration data
+    flow: the degridding reads coordinates, y and v and writes r (32 B per visibility) and
+    reads the grid once (32N); the gridding of step 9 reads r and the coordinates and writes
+    v (24 B per visibility) and writes its grid once (32N).  This build's own extra traffic
+    (its running grid sum, the separate halo pass) is not counted as algorithmic."""
     N = n * n
     nw = wavelets
     return {
         "fft_rows": 4 * N + 16 * N,                  # read x~, write n x 2n complex rows
         "fft_cols": 16 * N + 32 * N,                 # read the rows, write the 2n x 2n grid
-        "degrid": 32 * M_active + 32 * N,            # coords, y, v in; e out; grid read once
-        "grid": 32 * M_active + 64 * N,              # coords, e, v in; v out; running grid sum in+out
+        "degrid": 32 * M_active + 32 * N,
+        "grid": 24 * M_active + 32 * N,
         "ifft_cols": 32 * N + 16 * N,
         # row pass with steps 17-18: rows, s~ and x in; x and x~ out
         "ifft_rows": 16 * N + 4 * N * 2 + 4 * N * 2,
@@ -73,16 +81,90 @@ def stage_bytes(n, M_active, wavelets=8):
     }
 
 
-def traffic_from_profile(kernel_stage):
-    """HBM bytes per launch from a committed counter summary, if it still matches the source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel_stage}_{WORKLOAD}_traffic.json")
+def phi_bytes(n, M):
+    """Phi (or Phi^dagger): x 4N, pruned FFT (rows 16N out, 16N in, 32N out), degridding
+    with the grid read once (32N) plus coordinates and y (16 B per visibility): 100N + 16M."""
+    return 100 * n * n + 16 * M
+
+
+def profile_record(kernel_stage, workload):
+    """A committed counter record for a kernel, if it still matches the kernel's source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_stage}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     src = os.path.join(ROOT, rec["source"])
     if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
         return None
-    return rec.get("bytes_per_launch")
+    rec["path"] = os.path.relpath(path, ROOT)
+    return rec
+
+
+def make_problem(w, R, tune, phi_iters=50):
+    """Plan, noisy data in plan order, radii, ||Phi|| (power iteration on the GPU)."""
+    import torch
+
+    import synth
+
+    t0 = time.time()
+    inp = synth.make_inputs(w)
+    plan = R.Plan(w.n, inp.uv, inp.block_off, **tune)
+    order = plan.order()
+    x_true = torch.tensor(inp.x_true, dtype=torch.float32, device="cuda")
+    y0 = plan.phi(x_true).cpu().numpy()
+    y0_user = np.empty_like(y0)
+    y0_user[order] = y0
+    y_user, sig, eps = synth.add_noise(w, y0_user.astype(np.complex128), inp.block_off)
+    y_plan = torch.tensor(y_user[order], dtype=torch.complex64, device="cuda")
+    x0 = torch.tensor(synth.power_start(w.n, w.seed(synth.SEED_POWER)), dtype=torch.float32, device="cuda")
+    phi_norm, _ = plan.norm(x0, max_it=phi_iters, rtol=0.0)
+    log(f"{w.name}: setup {time.time() - t0:.1f}s, {plan.n_items} items, ||Phi|| ~ {phi_norm:.5g}")
+    return dict(inp=inp, plan=plan, x_true=x_true, y_user=y_user, y_plan=y_plan, eps=eps, phi_norm=phi_norm)
+
+
+def time_run(sol, schedule, warmup, steps, refresh=64, seed=0):
+    """ms per iteration of graph-replayed batched steps with the device-side block selection,
+    the running-sum refresh every `refresh` iterations inside the timed region, and the mean
+    number of active blocks and visibilities per timed iteration."""
+    import torch
+
+    r = sol.prepare(warmup + steps, schedule, graph=True, seed=seed)
+    for t in range(warmup):
+        r.step()
+        if refresh and (t + 1) % refresh == 0:
+            sol.pd.refresh()
+    torch.cuda.synchronize()
+    t_a = time.perf_counter()
+    for t in range(warmup, warmup + steps):
+        r.step()
+        if refresh and (t + 1) % refresh == 0:
+            sol.pd.refresh()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t_a) * 1e3 / steps
+    masks = np.array(r.history()["masks"][warmup:], dtype=np.float64)
+    sizes = np.diff(sol.plan.block_off).astype(np.float64)
+    return ms, float(masks.sum(1).mean()), float((masks @ sizes).mean())
+
+
+def time_ops(plan, x, y, reps):
+    """Mean ms of Phi and of Phi^dagger (HIP events on the current stream)."""
+    import torch
+
+    yb = torch.empty(plan.M, dtype=torch.complex64, device="cuda")
+    xb = torch.empty(plan.n, plan.n, dtype=torch.float32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    for _ in range(3):
+        plan.phi(x, yb)
+        plan.phi_adj(y, xb)
+    ev[0].record()
+    for _ in range(reps):
+        plan.phi(x, yb)
+    ev[1].record()
+    for _ in range(reps):
+        plan.phi_adj(y, xb)
+    ev[2].record()
+    torch.cuda.synchronize()
+    return ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
 
 
 def main():
@@ -93,14 +175,16 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--op-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--tile", type=int, default=0, help="grid tile side (0: library default)")
-    ap.add_argument("--bin", type=int, default=0, help="max visibilities per work item (0: library default)")
+    ap.add_argument("--no-graph", action="store_true", help="eager steps only (for counter runs)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the adaptive and 2048^2 operating points (for short profiling runs)")
+    ap.add_argument("--tile", type=int, default=0, help="grid tile side (0: the autotuner's pick)")
+    ap.add_argument("--bin", type=int, default=0, help="max visibilities per work item (0: the autotuner's pick)")
     ap.add_argument("--wgs", type=int, default=0, help="workgroups of the persistent kernels (0: library default)")
-    ap.add_argument("--autotune", action="store_true",
-                    help="time the autotuner's candidates on this workload and use the fastest")
     ap.add_argument("--slice-vis", type=int, default=0,
-                    help="max visibilities per gridding workgroup of one tile (0: default, -1: no split)")
+                    help="max visibilities per gridding workgroup of one tile (0: the autotuner's pick, -1: no split)")
+    ap.add_argument("--tune-cache", default=os.path.join(ROOT, "paper_1610_08895_amd", "tuning_cache.json"),
+                    help="autotuner cache (JSON); a missing entry is timed and stored")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also copy a buffer of this many MiB once (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -114,39 +198,36 @@ def main():
     import synth
     import paper_1610_08895_amd as R
     from paper_1610_08895_amd import _lib
-    from paper_1610_08895_amd.solver import Solver, snr
+    from paper_1610_08895_amd.solver import Schedule, Solver, snr
 
     _lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     w = synth.WORKLOADS[WORKLOAD]
     t0 = time.time()
-    inp = synth.make_inputs(w)
-    log(f"inputs {time.time() - t0:.1f}s")
-    tuned = None
-    if args.autotune:
+
+    # ---- tuning: the autotuner's pick for this workload (cached per device and size) ----
+    tune_src = "command line"
+    if args.tile or args.bin or args.slice_vis:
+        tune = {"tile": args.tile, "bin": args.bin, "slice_vis": args.slice_vis}
+    else:
         from paper_1610_08895_amd import autotune
 
+        inp0 = synth.make_inputs(w)
         rng = np.random.default_rng(0)
         y_probe = rng.standard_normal(w.M) + 1j * rng.standard_normal(w.M)
-        tuned, _ = autotune.tune(w.n, inp.uv, inp.block_off, y_probe, np.full(w.d, 1.0), log=log)
-        args.tile, args.bin, args.slice_vis = tuned["tile"], tuned["bin"], tuned["slice_vis"]
-        log(f"autotuned {tuned} ({time.time() - t0:.1f}s)")
-    plan = R.Plan(w.n, inp.uv, inp.block_off, tile=args.tile, bin=args.bin, slice_vis=args.slice_vis,
-                  persistent_wgs=args.wgs)
-    order = plan.order()
-    log(f"plan {time.time() - t0:.1f}s items={plan.n_items}")
-    x_true = torch.tensor(inp.x_true, dtype=torch.float32, device="cuda")
-    y0 = plan.phi(x_true).cpu().numpy()
-    y0_user = np.empty_like(y0)
-    y0_user[order] = y0
-    y_user, sig, eps = synth.add_noise(w, y0_user.astype(np.complex128), inp.block_off)
-    y_plan = torch.tensor(y_user[order], dtype=torch.complex64, device="cuda")
+        had = autotune.cached(args.tune_cache, w.n, w.M, w.d)
+        tune, _ = autotune.tune(w.n, inp0.uv, inp0.block_off, y_probe, np.full(w.d, 1.0), cache=args.tune_cache,
+                                log=log)
+        tune_src = "autotuner cache" if had else "autotuner (timed in this run)"
+        log(f"tuning {tune} from the {tune_src} ({time.time() - t0:.1f}s)")
+        del inp0
+    tune = dict(tune, persistent_wgs=args.wgs)
+    P = make_problem(w, R, tune)
+    plan, inp, y_plan, eps, phi_norm = P["plan"], P["inp"], P["y_plan"], P["eps"], P["phi_norm"]
     sara = R.Sara(w.n, 4)
-    x0 = torch.tensor(synth.power_start(w.n, w.seed(synth.SEED_POWER)), dtype=torch.float32, device="cuda")
-    phi_norm, _ = plan.norm(x0, max_it=50, rtol=0.0)
     psi_norm = 3.0
-    log(f"setup {time.time() - t0:.1f}s ||Phi|| ~ {phi_norm:.4g}")
+    tile_used = plan.tile
 
     if args.copy_probe_mib:
         src = torch.ones(args.copy_probe_mib * (1 << 18), dtype=torch.float32, device="cuda")
@@ -155,31 +236,26 @@ def main():
         del src, dst
         log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
 
+    # ---- headline: p = 1, graph-replayed iterations, running-sum refresh every 64 ----
     sol = Solver(plan, sara, y_plan, eps, psi_norm, phi_norm)
-    ones = np.ones(plan.d, np.uint8)
-    use_graph = not args.no_graph
-    for _ in range(args.warmup):
-        sol.step(ones)
-    if use_graph:
-        sol.capture()
-        sol.step(ones, graph=True)
-    torch.cuda.synchronize()
-
-    # ---- timed region: K iterations ----
-    torch.cuda.synchronize()
-    t_a = time.perf_counter()
-    for _ in range(args.steps):
-        sol.step(ones, graph=use_graph)
-    torch.cuda.synchronize()
-    t_b = time.perf_counter()
-    ms_per_step = (t_b - t_a) * 1e3 / args.steps
+    if args.no_graph:
+        for _ in range(args.warmup):
+            sol.step()
+        torch.cuda.synchronize()
+        t_a = time.perf_counter()
+        for _ in range(args.steps):
+            sol.step()
+        torch.cuda.synchronize()
+        ms_per_step = (time.perf_counter() - t_a) * 1e3 / args.steps
+    else:
+        ms_per_step, _, _ = time_run(sol, Schedule(), args.warmup, args.steps)
     iters_s = 1e3 / ms_per_step
-    log(f"batched{'+graph' if use_graph else ''}: {ms_per_step:.4f} ms/iter = {iters_s:.1f} iters/s")
+    log(f"batched{'' if args.no_graph else '+graph'} p=1: {ms_per_step:.4f} ms/iter = {iters_s:.1f} iters/s")
 
     # ---- per-stage HIP-event timings (eager steps, events on each stage's stream) ----
     sol.pd.timing(True)
     for _ in range(args.steps):
-        sol.step(ones)
+        sol.step()
     stages = sol.pd.stage_times()
     sol.pd.timing(False)
     mean_ms = {k: v[0] / v[1] for k, v in stages.items() if v[1]}
@@ -190,40 +266,29 @@ def main():
     achieved = alg / (mean_ms[dom] * 1e-3) / 1e9
     log("stages (mean ms/launch): " + ", ".join(f"{k}={v:.4f}" for k, v in mean_ms.items()))
 
-    # ---- plain per-block form ----
+    # ---- plain per-block form (same kernels, one gather/scatter launch per block) ----
     plain_ms = None
     if args.plain_steps > 0:
+        for _ in range(2):
+            sol.step(plain=True)
         torch.cuda.synchronize()
         t_a = time.perf_counter()
         for _ in range(args.plain_steps):
-            sol.step(ones, plain=True)
+            sol.step(plain=True)
         torch.cuda.synchronize()
         plain_ms = (time.perf_counter() - t_a) * 1e3 / args.plain_steps
     snr_db = snr(inp.x_true, sol.x())
     log(f"plain: {plain_ms} ms/iter; SNR after {sol.pd.iteration} iterations {snr_db:.2f} dB")
 
     # ---- Phi and Phi^dagger alone ----
-    yb = torch.empty(plan.M, dtype=torch.complex64, device="cuda")
-    xb = torch.empty(w.n, w.n, dtype=torch.float32, device="cuda")
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    for _ in range(3):
-        plan.phi(x_true, yb)
-        plan.phi_adj(y_plan, xb)
-    ev[0].record()
-    for _ in range(args.op_reps):
-        plan.phi(x_true, yb)
-    ev[1].record()
-    for _ in range(args.op_reps):
-        plan.phi_adj(y_plan, xb)
-    ev[2].record()
-    torch.cuda.synchronize()
-    phi_ms = ev[0].elapsed_time(ev[1]) / args.op_reps
-    phia_ms = ev[1].elapsed_time(ev[2]) / args.op_reps
+    phi_ms, phia_ms = time_ops(plan, P["x_true"], y_plan, args.op_reps)
+    pb = phi_bytes(w.n, w.M)
     log(f"Phi {phi_ms:.4f} ms ({w.M / phi_ms / 1e6:.1f} Gvis/s), Phi^dagger {phia_ms:.4f} ms "
         f"({w.M / phia_ms / 1e6:.1f} Gvis/s)")
     # ---- Eq. 13 at x for every block (the adaptive schedule's exact refresh) ----
     rs = torch.empty(plan.d, 2, dtype=torch.float64, device="cuda")
     sol.pd.residual(rs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ev[0].record()
     for _ in range(args.op_reps):
         sol.pd.residual(rs)
@@ -231,32 +296,72 @@ def main():
     torch.cuda.synchronize()
     resid_ms = ev[0].elapsed_time(ev[1]) / args.op_reps
     log(f"Eq. 13 refresh (all blocks at x) {resid_ms:.4f} ms")
+    del sol
+
+    # ---- the method's operating point: Eq. 14 with sum p = 16 of 64 blocks ----
+    extra = {}
+    if not args.no_extra:
+        sol_a = Solver(plan, sara, y_plan, eps, psi_norm, phi_norm)
+        sch = Schedule("adaptive", n_nodes=16.0, p_min=0.05, p_max=0.5)
+        ms_a, nb_a, nv_a = time_run(sol_a, sch, args.warmup, args.steps, seed=1)
+        extra["adaptive16"] = {
+            "schedule": "Eq. 14, sum p = 16, p_min 0.05, p_max 0.5 (c_i from each step's residuals)",
+            "iters_s": round(1e3 / ms_a, 2), "ms_per_step": round(ms_a, 5), "mean_active_blocks": round(nb_a, 2),
+            "mean_active_vis": round(nv_a), "active_gvis_s": round(nv_a / ms_a / 1e6, 2)}
+        log(f"adaptive16: {ms_a:.4f} ms/iter, {nb_a:.1f} blocks / {nv_a / 1e6:.2f} M vis active")
+        del sol_a
 
     # ---- CPU oracle baseline: one iteration of Algorithm 1 on the same workload ----
     cpu = None
     if not args.no_cpu_baseline:
+        from oracle import parallel
         from oracle import pd as opd
         from oracle.measurement import Measurement
         from oracle.wavelets import Sara as OSara
 
+        cores = len(os.sched_getaffinity(0))
+        parallel.set_workers(cores)
         meas = Measurement(inp.uv, inp.block_off, (w.n, w.n))
         osara = OSara(w.n)
-        for i in range(meas.d):
-            meas.cells(i)
+        parallel.pmap(meas.cells, range(meas.d))
         prm = opd.default_params(psi_norm, phi_norm)
-        yb_o = opd.split_blocks(meas, y_user)
+        yb_o = opd.split_blocks(meas, P["y_user"])
         st = opd.init_state(meas, osara)
         mask = np.ones(meas.d, bool)
         t_a = time.perf_counter()
         opd.iteration(meas, osara, yb_o, eps, prm, st, mask)
         t_cpu = time.perf_counter() - t_a
-        cpu = {"value": 1.0 / t_cpu, "unit": "iters/s", "cores": 1, "kind": "oracle",
-               "sample": f"1 iteration of Algorithm 1 on the full {WORKLOAD} workload, all 64 blocks "
-                         f"active, FP64 numpy/scipy (single-threaded), {t_cpu:.1f} s; host has "
-                         f"{len(os.sched_getaffinity(0))} cores available"}
-        log(f"cpu oracle: {t_cpu:.2f} s / iteration")
+        cpu = {"value": 1.0 / t_cpu, "unit": "iters/s", "cores": cores, "kind": "oracle",
+               "sample": f"1 iteration of Algorithm 1 on the full {WORKLOAD} workload, all 64 blocks active, "
+                         f"FP64 numpy, the par-for over blocks and the per-basis wavelet loop on a pool of "
+                         f"{cores} threads, {t_cpu:.1f} s"}
+        log(f"cpu oracle: {t_cpu:.2f} s / iteration on {cores} threads")
+        del meas, osara, st
 
-    traffic = traffic_from_profile(dom)
+    # ---- the large case: 2048^2, M = 2^24 in 128 blocks, Eq. 14 at mean p = 0.25 ----
+    if not args.no_extra:
+        del P, plan
+        torch.cuda.empty_cache()
+        w5 = synth.WORKLOADS["n2048_m16m_d128"]
+        P5 = make_problem(w5, R, {})
+        sol5 = Solver(P5["plan"], R.Sara(w5.n, 4), P5["y_plan"], P5["eps"], psi_norm, P5["phi_norm"])
+        sch5 = Schedule("adaptive", n_nodes=32.0, p_min=0.05, p_max=0.5)
+        ms5, nb5, nv5 = time_run(sol5, sch5, 10, 50, seed=2)
+        ms5_p1, _, _ = time_run(sol5, Schedule(), 5, 20)
+        phi5, phia5 = time_ops(P5["plan"], P5["x_true"], P5["y_plan"], 5)
+        pb5 = phi_bytes(w5.n, w5.M)
+        extra["n2048_m16m_d128"] = {
+            "schedule": "Eq. 14, sum p = 32 of 128 (mean 0.25), p_min 0.05, p_max 0.5",
+            "iters_s": round(1e3 / ms5, 2), "ms_per_step": round(ms5, 5), "mean_active_blocks": round(nb5, 2),
+            "mean_active_vis": round(nv5), "active_gvis_s": round(nv5 / ms5 / 1e6, 2),
+            "p1_iters_s": round(1e3 / ms5_p1, 2),
+            "phi_gvis_s": round(w5.M / phi5 / 1e6, 2), "phi_adj_gvis_s": round(w5.M / phia5 / 1e6, 2),
+            "phi_frac": round(pb5 / (phi5 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "phi_adj_frac": round(pb5 / (phia5 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"n2048: adaptive32 {ms5:.4f} ms/iter ({nb5:.1f} blocks, {nv5 / 1e6:.2f} M vis), p=1 {ms5_p1:.4f} ms, "
+            f"Phi {phi5:.4f} ms, Phi^dagger {phia5:.4f} ms")
+
+    rec = profile_record(dom, WORKLOAD)
     out = {
         "metric": METRIC,
         "value": round(iters_s, 3),
@@ -270,21 +375,31 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": w.n, "M": w.M, "d": plan.d, "p": 1.0, "tile": plan.tile,
-                   "bin": args.bin or 1024, "slice_vis": args.slice_vis or -1, "autotuned": tuned is not None,
-                   "form": "batched persistent kernels" + (" + HIP graph" if use_graph else ""),
+        "config": {"workload": WORKLOAD, "n": w.n, "M": w.M, "d": w.d, "p": 1.0, "tile": tile_used,
+                   "bin": tune.get("bin") or 1024, "slice_vis": tune.get("slice_vis") or -1,
+                   "autotuned": tune_src != "command line", "tuning_source": tune_src,
+                   "form": "batched persistent kernels" + ("" if args.no_graph else " + HIP graph") +
+                           ", device-side block selection, running-sum refresh every 64 iterations",
                    "kernel": "Kaiser-Bessel 8x8, 2x oversampling", "sara": "Dirac + db1..db8, 4 levels"},
         "phi_gvis_s": round(w.M / phi_ms / 1e6, 2),
         "phi_adj_gvis_s": round(w.M / phia_ms / 1e6, 2),
+        "phi_frac": round(pb / (phi_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "phi_adj_frac": round(pb / (phia_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "phi_algorithmic_bytes": pb,
         "eq13_refresh_ms": round(resid_ms, 4),
         "plain_iters_s": round(1e3 / plain_ms, 3) if plain_ms else None,
         "speedup_vs_plain": round(plain_ms / ms_per_step, 3) if plain_ms else None,
         "stage_algorithmic_bytes": sb,
         "snr_db": round(snr_db, 3),
         "stage_ms_per_launch": {k: round(v, 5) for k, v in mean_ms.items()},
-        "roofline": {"kernel": dom, "kernel_symbol": STAGE_KERNEL.get(dom, dom).format(T=args.tile or 32), "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"kernel": dom, "kernel_symbol": STAGE_KERNEL.get(dom, dom).format(T=tile_used),
+                     "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "algorithmic_bytes": alg},
+                     "traffic": rec["bytes_per_launch"] if rec else None,
+                     "traffic_source": f"stored: {rec['path']} (counters of this kernel source)" if rec else None,
+                     "limiter": rec.get("limiter") if rec else None,
+                     "algorithmic_bytes": alg},
+        **extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -180,8 +180,10 @@ void ri_pd_destroy(ri_pd pd);
  */
 int ri_pd_step(ri_pd pd, const uint8_t* mask, double* stats, hipStream_t stream);
 
-/* The same iteration in the plain form: one launch per active block for each data-term
- * operator, no persistent worklist.  mask_host: host d uint8 (NULL = all). */
+/* The same iteration in the plain form: one degridding and one gridding launch per active
+ * block (over that block's own tiles; one halo pass merges all blocks' tile borders after
+ * the last one) instead of one launch over all active blocks.  The rest of the step is
+ * the batched step's.  mask_host: host d uint8 (NULL = all), copied to the device. */
 int ri_pd_step_plain(ri_pd pd, const uint8_t* mask_host, double* stats, hipStream_t stream);
 
 /* Rebuild sum_i M_i^dagger v~_i from the stored v (all blocks).  The batched and plain steps
@@ -212,7 +214,7 @@ enum {
                                applies steps 17-18 to its output                          */
   RI_STAGE_PSI_ADJ = 8,     /* Psi^dagger x~ and dual clip, all levels (step 13)            */
   RI_STAGE_PSI_SYNTH = 9,   /* s~ = Psi s, all levels (step 14)                             */
-  RI_STAGE_UPDATE = 10,     /* steps 17-18, elementwise (ri_pd_step_plain only)             */
+  RI_STAGE_UPDATE = 10,     /* not recorded: both forms apply steps 17-18 in IFFT_ROWS      */
   RI_STAGE_COUNT = 11
 };
 
@@ -273,6 +275,49 @@ int ri_residual_energy(const double* resid_norm, const double* eps, int d, doubl
  * Needs 0 < p_min <= n/d <= p_max <= 1 and c_i >= 0 (RI_EINVAL otherwise).  a_out may be NULL. */
 int ri_probs(const double* c, int d, double n_nodes, double p_min, double p_max, double* p_out,
              double* a_out);
+
+/* ------------------------------------------------------------------------------------
+ * Block selection on the device (Algorithm 1 step 3; Sec. III-B; Sec. IV Eqs. 13-14)
+ *
+ * One call enqueues one single-workgroup kernel, so a step and its draw can be captured
+ * together in a graph and replayed with no host round trip between iterations.  All
+ * pointers are device pointers owned by the caller; every field the flags do not use
+ * may be NULL / 0.
+ * ------------------------------------------------------------------------------------ */
+typedef struct {
+  int d;                     /* number of blocks, 1 <= d <= 4096                          */
+  int64_t T;                 /* rows of u / masks / logs; iteration t uses row t mod T     */
+  const double* u;           /* T x d float64 U[0,1) variates: block i is active at t iff
+                                u[t][i] < p_i (Sec. III-B: independent draws)              */
+  const uint8_t* masks;      /* T x d masks to replay instead of drawing (or NULL)         */
+  const double* p_fixed;     /* d probabilities when RI_SCHED_ADAPTIVE is not set (NULL: 1) */
+  double* c;                 /* d Eq. 13 energies c_i (state of the adaptive rule)          */
+  const double* stats_step;  /* d x 2 float64 stats of the last ri_pd_step (RI_SCHED_UPDATE) */
+  const double* stats_x;     /* d x 2 float64 output of ri_pd_residual (RI_SCHED_REFRESH)   */
+  const double* eps;         /* d radii eps_i                                             */
+  double n_nodes;            /* Eq. 14: sum_i p_i = n_nodes                                */
+  double p_min, p_max;       /* Eq. 14 bounds, 0 < p_min <= n_nodes/d <= p_max <= 1        */
+  int64_t* counter;          /* iteration index t; RI_SCHED_DRAW reads it and adds 1       */
+  uint8_t* mask;             /* d: on entry the last step's mask (RI_SCHED_UPDATE reads it);
+                                RI_SCHED_DRAW overwrites it with the mask of iteration t   */
+  double* p_log;             /* T x d or NULL: RI_SCHED_DRAW stores p of iteration t in row t mod T */
+  uint8_t* mask_log;         /* T x d or NULL: the drawn mask, likewise                    */
+} ri_sched;
+
+enum {
+  RI_SCHED_UPDATE = 1,   /* c_i <- Eq. 13 of stats_step[2i+1] (= ||Phi_i x~ - y_i||^2) for the
+                            blocks of the last step's mask; skipped while counter == 0    */
+  RI_SCHED_REFRESH = 2,  /* c_i <- Eq. 13 of stats_x[2i+1] (= ||Phi_i x - y_i||^2) for all i */
+  RI_SCHED_ADAPTIVE = 4, /* p_i from c by Eq. 14 (p_i = n/d when sum c = 0); else p_fixed    */
+  RI_SCHED_DRAW = 8      /* mask of iteration t = counter from row t mod T, then counter += 1 */
+};
+
+/* Apply the flagged parts in the order UPDATE, REFRESH, then (with DRAW) the
+ * probabilities and the draw.  Sums over blocks are formed in a fixed order, so equal
+ * inputs give bitwise equal results.  Errors: RI_EINVAL (NULL a, d out of range, unknown
+ * flags, a pointer a flag needs is NULL, T < 1 with DRAW, Eq. 14 bounds violated with
+ * ADAPTIVE), RI_EHIP.  c must hold finite values >= 0. */
+int ri_sched_step(const ri_sched* a, int flags, hipStream_t stream);
 
 #ifdef __cplusplus
 }

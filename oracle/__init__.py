@@ -15,7 +15,9 @@ Contents, each citing the passage it follows:
   probs          Eqs. 13 and 14
   power          power method for operator norms (Sec. V)
   pd             Algorithm 1
+  reweight       the weighted l1 prior of reweighted SARA and its reweighting loop
   metrics        Eq. 15 and objective / feasibility diagnostics
+  parallel       optional thread pool for the par-for over blocks and the per-basis loop
 
 Every function is pinned by tests marked ``not gpu`` against something other than
 itself (closed forms, brute force, textbook routines, invariants); see the pin list

@@ -32,6 +32,7 @@ import dataclasses
 
 import numpy as np
 
+from .parallel import pmap
 from .probs import adaptive_probabilities, residual_energy
 from .prox import data_dual_update, proj_pos, sparsity_dual_update
 
@@ -68,10 +69,12 @@ class State:
     v: list
     vt: list
     t: int = 0
+    w: np.ndarray | None = None  # per-coefficient weights of a weighted l1 prior (None: all 1)
 
     def copy(self):
         return State(self.x.copy(), self.xt.copy(), self.s.copy(),
-                     [a.copy() for a in self.v], [a.copy() for a in self.vt], self.t)
+                     [a.copy() for a in self.v], [a.copy() for a in self.vt], self.t,
+                     None if self.w is None else self.w.copy())
 
 
 def init_state(meas, sara):
@@ -96,16 +99,23 @@ def iteration(meas, sara, y_blocks, eps, prm: Params, st: State, active):
     stats = np.full((d, 2), np.nan)
 
     b_full = meas.F(meas.Z(st.xt))                                  # step 4
-    for i in np.flatnonzero(active):                                # steps 5-10
+
+    def data_block(i):                                              # steps 5-10, block i
         b_i = meas.Mi(i, b_full)                                    # step 5
         Gb = meas.Gi(i, b_i)
-        stats[i, 0] = np.linalg.norm(st.v[i] + Gb - y_blocks[i])
-        stats[i, 1] = np.linalg.norm(Gb - y_blocks[i])
-        st.v[i] = data_dual_update(st.v[i], Gb, y_blocks[i], eps[i])  # step 8
-        st.vt[i] = meas.GiH(i, st.v[i])                             # step 9
+        r0 = np.linalg.norm(st.v[i] + Gb - y_blocks[i])
+        r1 = np.linalg.norm(Gb - y_blocks[i])
+        v_i = data_dual_update(st.v[i], Gb, y_blocks[i], eps[i])    # step 8
+        return r0, r1, v_i, meas.GiH(i, v_i)                        # step 9
+
+    act = np.flatnonzero(active)
+    for i, (r0, r1, v_i, vt_i) in zip(act, pmap(data_block, act)):  # the par-for over A
+        stats[i] = r0, r1
+        st.v[i], st.vt[i] = v_i, vt_i
     # step 11: v_i, v~_i of inactive blocks are left as they are
 
-    st.s = sparsity_dual_update(st.s, sara.adj(st.xt), prm.alpha)   # step 13
+    thr = prm.alpha if st.w is None else prm.alpha * st.w
+    st.s = sparsity_dual_update(st.s, sara.adj(st.xt), thr)         # step 13
     s_tilde = sara.fwd(st.s)                                        # step 14
 
     acc = np.zeros(meas.Ky * meas.Kx, dtype=np.complex128)          # sum_i M_i^dagger v~_i

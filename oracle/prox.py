@@ -24,11 +24,13 @@ def proj_l2ball(z, y, eps):
 
 
 def soft(z, alpha):
+    """S_alpha(z); alpha a scalar or one threshold per entry (the weighted l1 norm)."""
     z = np.asarray(z)
     mag = np.abs(z)
     out = np.zeros_like(z)
     nz = mag > 0
-    out[nz] = z[nz] * np.maximum(mag[nz] - alpha, 0.0) / mag[nz]
+    a = np.broadcast_to(np.asarray(alpha, dtype=np.float64), z.shape)[nz]
+    out[nz] = z[nz] * np.maximum(mag[nz] - a, 0.0) / mag[nz]
     return out
 
 
@@ -43,6 +45,7 @@ def data_dual_update(v, Gb, y, eps):
 
 
 def sparsity_dual_update(s, w, alpha):
-    """Algorithm 1 step 13: (s + w) - S_alpha(s + w), w = Psi^dagger x~."""
+    """Algorithm 1 step 13: (s + w) - S_alpha(s + w), w = Psi^dagger x~.  With alpha an array
+    of per-coefficient thresholds this is the step for the weighted l1 prior."""
     z = s + w
     return z - soft(z, alpha)

@@ -32,6 +32,8 @@ import math
 
 import numpy as np
 
+from .parallel import pmap
+
 
 def daubechies(N: int) -> np.ndarray:
     """Minimum-phase Daubechies lowpass filter with N vanishing moments (length 2N)."""
@@ -121,7 +123,7 @@ class Sara:
     def adj(self, x):
         """Psi^dagger x -> (b, n, n)."""
         out = [np.array(x, dtype=np.float64)] if self.dirac else []
-        out += [dwt2(x, h, self.levels) for h in self.filters]
+        out += pmap(lambda h: dwt2(x, h, self.levels), self.filters)
         return np.stack(out)
 
     def fwd(self, s):
@@ -131,7 +133,6 @@ class Sara:
         if self.dirac:
             acc += s[0]
             k = 1
-        for h in self.filters:
-            acc += idwt2(s[k], h, self.levels)
-            k += 1
+        for part in pmap(lambda kh: idwt2(s[kh[0]], kh[1], self.levels), list(enumerate(self.filters, start=k))):
+            acc += part  # summed in basis order
         return acc

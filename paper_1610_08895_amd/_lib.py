@@ -31,6 +31,15 @@ class PDParams(ctypes.Structure):
                 ("psi_norm", c_double), ("phi_norm", c_double)]
 
 
+class Sched(ctypes.Structure):
+    _fields_ = [("d", c_int), ("T", c_int64), ("u", c_void_p), ("masks", c_void_p), ("p_fixed", c_void_p),
+                ("c", c_void_p), ("stats_step", c_void_p), ("stats_x", c_void_p), ("eps", c_void_p),
+                ("n_nodes", c_double), ("p_min", c_double), ("p_max", c_double), ("counter", c_void_p),
+                ("mask", c_void_p), ("p_log", c_void_p), ("mask_log", c_void_p)]
+
+
+SCHED_UPDATE, SCHED_REFRESH, SCHED_ADAPTIVE, SCHED_DRAW = 1, 2, 4, 8
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "ri_last_error": (ctypes.c_char_p, []),
@@ -66,6 +75,7 @@ SIGNATURES = {
                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ri_residual_energy": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
     "ri_probs": (c_int, [c_void_p, c_int, c_double, c_double, c_double, c_void_p, P(c_double)]),
+    "ri_sched_step": (c_int, [P(Sched), c_int, c_void_p]),
 }
 
 _lib = None

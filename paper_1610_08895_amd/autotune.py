@@ -30,6 +30,14 @@ def _key(n, M, d):
     return f"{torch.cuda.get_device_name(0)}|n={n}|M={M}|d={d}"
 
 
+def cached(cache, n, M, d):
+    """True when the cache holds a choice for this problem size on this device."""
+    if not cache or not os.path.exists(cache):
+        return False
+    with open(cache) as f:
+        return _key(n, M, d) in json.load(f)
+
+
 def time_candidate(n, uv, block_off, y_user, eps, tune, steps=10, warmup=3):
     """Mean milliseconds per batched PD step with the given tuning (all blocks active)."""
     plan = Plan(n, uv, block_off, **tune)
@@ -51,7 +59,7 @@ def time_candidate(n, uv, block_off, y_user, eps, tune, steps=10, warmup=3):
     return ms
 
 
-def tune(n, uv, block_off, y_user, eps, candidates=DEFAULT_CANDIDATES, steps=10, cache=None, log=None):
+def tune(n, uv, block_off, y_user, eps, candidates=DEFAULT_CANDIDATES, steps=20, cache=None, log=None):
     """Returns (best tuning dict, {candidate index: ms}).  cache: JSON path or None."""
     uv = np.asarray(uv, np.float32)
     M, d = uv.shape[0], len(block_off) - 1
@@ -61,11 +69,15 @@ def tune(n, uv, block_off, y_user, eps, candidates=DEFAULT_CANDIDATES, steps=10,
             stored = json.load(f)
         if key in stored:
             return dict(stored[key]["tune"]), {}
+    # two interleaved rounds, best of each candidate: a drift of the clock or of other load
+    # during the sweep then does not favour whichever candidate ran at the quiet moment
     times = {}
-    for k, cand in enumerate(candidates):
-        times[k] = time_candidate(n, uv, block_off, y_user, eps, cand, steps=steps)
-        if log:
-            log(f"autotune {cand}: {times[k]:.4f} ms/step")
+    for rnd in range(2):
+        for k, cand in enumerate(candidates):
+            ms = time_candidate(n, uv, block_off, y_user, eps, cand, steps=steps)
+            times[k] = min(times.get(k, ms), ms)
+            if log:
+                log(f"autotune {cand} (round {rnd + 1}): {ms:.4f} ms/step")
     best = dict(candidates[min(times, key=times.get)])
     if cache:
         stored = {}

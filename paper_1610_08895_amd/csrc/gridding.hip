@@ -285,7 +285,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
                                                    const float2* __restrict__ e, float2* __restrict__ v,
                                                    const float* __restrict__ shrink,
                                                    const int* __restrict__ unit_patch, float2* __restrict__ spatch,
-                                                   int fresh) {
+                                                   int fresh, int ring_add) {
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int R0 = KB_J / 2 - 1;  // reach before the tile
   constexpr int NV = MAX_BIN / GGT;
@@ -463,7 +463,13 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
           *g = make_float2(old.x + a.x, old.y + a.y);
         }
       } else if (sp < 0) {
-        patch[ring_index<T>(ly, lx)] = a;  // the ring
+        float2* h = &patch[ring_index<T>(ly, lx)];  // the ring
+        if (!ring_add) {
+          *h = a;
+        } else if (a.x != 0.f || a.y != 0.f) {
+          const float2 old = *h;
+          *h = make_float2(old.x + a.x, old.y + a.y);
+        }
       } else {
         patch[c] = a;  // a further slice's whole region
       }
@@ -474,13 +480,13 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
 // Adds the halo patches of the eight neighbours of each tile into its interior cells
 // within reach of its edges (3 cells from the far edge, 4 from the near edge).  Each patch
 // cell outside its tile lies in exactly one other tile's interior, so it has exactly one
-// reader; with CLEAR the reader zeroes it, so that all patches are zero again when the
-// kernel ends (a tile not gridded in a later launch then contributes nothing).  Where the
-// tile or a neighbour has slice patches (sp_off not null), their cells that fall in this
-// tile's interior are added too, in a fixed order; every slice rewrites its whole patch
-// in each gridding launch, so those are only read.
-template <int T, bool CLEAR>
-__global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, float2* __restrict__ grid, int K,
+// reader.  The patches are only read: the batched gridding rewrites the whole ring of
+// every tile with visibilities in each launch, and the per-block form zeroes all rings
+// before its first block and accumulates into them.  Where the tile or a neighbour has
+// slice patches (sp_off not null), their cells that fall in this tile's interior are added
+// too, in a fixed order; every slice rewrites its whole patch in each gridding launch.
+template <int T>
+__global__ __launch_bounds__(GT) void k_grid_halo(const float2* __restrict__ halo, float2* __restrict__ grid, int K,
                                                   int tpa, const int* __restrict__ sp_off,
                                                   const int* __restrict__ sp_list,
                                                   const float2* __restrict__ spatch) {
@@ -523,11 +529,9 @@ __global__ __launch_bounds__(GT) void k_grid_halo(float2* __restrict__ halo, flo
         if (ly < 0 || ly >= TW || lx < 0 || lx >= TW) continue;
         const int nt = ((ty + dy + tpa) & (tpa - 1)) * tpa + ((tx + dx + tpa) & (tpa - 1));
         if (dy != 0 || dx != 0) {
-          float2* hp = &halo[size_t(nt) * ring_cells(T) + ring_index<T>(ly, lx)];
-          const float2 h = *hp;
+          const float2 h = halo[size_t(nt) * ring_cells(T) + ring_index<T>(ly, lx)];
           acc.x += h.x;
           acc.y += h.y;
-          if (CLEAR && (h.x != 0.f || h.y != 0.f)) *hp = make_float2(0.f, 0.f);
         }
         if (slices)
           for (int j = sp_off[nt]; j < sp_off[nt + 1]; ++j) {
@@ -576,17 +580,13 @@ int wgs_for(const Plan& p, int units) {
   return units < g ? (units > 0 ? units : 1) : g;
 }
 
+// sliced: after a launch over the plan's tile slices (slice patches are merged too);
+// otherwise after the per-block launches, which never write slice patches.
 template <int T>
 void launch_halo(const Plan& p, float2* grid, bool sliced, hipStream_t s) {
   const bool sp = sliced && p.n_spatch > 0;
-  if (sliced) {
-    hipLaunchKernelGGL((k_grid_halo<T, false>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa,
-                       sp ? p.tile_sp_off : nullptr, sp ? p.tile_sp : nullptr, sp ? p.spatch : nullptr);
-    p.halo_dirty = true;
-  } else {
-    hipLaunchKernelGGL((k_grid_halo<T, true>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa,
-                       nullptr, nullptr, nullptr);
-  }
+  hipLaunchKernelGGL((k_grid_halo<T>), dim3(p.n_tiles), dim3(GT), 0, s, p.halo, grid, p.K, p.tpa,
+                     sp ? p.tile_sp_off : nullptr, sp ? p.tile_sp : nullptr, sp ? p.spatch : nullptr);
 }
 
 // units/items: the plan's tile slices over titems (sliced = true) or one block's units
@@ -603,15 +603,13 @@ __global__ __launch_bounds__(GT) void k_zero_tiles(float2* __restrict__ grid, in
 }
 
 // fresh: the launch overwrites the grid (tile interiors stored, tiles without
-// visibilities zeroed) instead of adding into it.
+// visibilities zeroed) instead of adding into it.  Over the plan's tile slices (sliced)
+// each tile's ring is overwritten; over one block's units it is added to, and the caller
+// zeroes the rings before the first block and runs the halo pass after the last.
 template <int T, int MODE>
 int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const Item* items, const uint8_t* mask,
                 float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
                 bool with_halo = true, bool fresh = false) {
-  if (!sliced && p.halo_dirty) {  // per-block gridding needs all-zero patches to start from
-    RI_TRY(zero_c64(p.halo, size_t(p.n_tiles) * ring_cells(T), s));
-    p.halo_dirty = false;
-  }
   if (fresh && p.n_empty > 0) {
     hipLaunchKernelGGL((k_zero_tiles<T>), dim3(p.n_empty), dim3(GT), 0, s, grid, p.K, p.tpa, p.empty_tiles);
     RI_LAUNCH_CHECK();
@@ -619,7 +617,7 @@ int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const
   if (nunits > 0) {
     hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GGT), 0, s, units, nunits, items,
                        p.item_box, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, shrink,
-                       sliced ? p.unit_patch : nullptr, p.spatch, fresh ? 1 : 0);
+                       sliced ? p.unit_patch : nullptr, p.spatch, fresh ? 1 : 0, sliced ? 0 : 1);
     RI_LAUNCH_CHECK();
   }
   if (with_halo) {
@@ -739,7 +737,23 @@ int grid_halo(const Plan& p, float2* grid, hipStream_t s) {
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const float* shrink, float2* grid,
                        hipStream_t s) {
   const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
-  return grid_units<GR_PROJECT>(p, false, p.bunits + a, b - a, p.items, nullptr, grid, nullptr, e, v, shrink, s);
+  return grid_units<GR_PROJECT>(p, false, p.bunits + a, b - a, p.items, nullptr, grid, nullptr, e, v, shrink, s,
+                                false);
+}
+
+int grid_blocks_begin(const Plan& p, hipStream_t s) {
+  return zero_c64(p.halo, size_t(p.n_tiles) * ring_cells(p.tile), s);
+}
+
+int grid_blocks_end(const Plan& p, float2* grid, hipStream_t s) {
+  switch (p.tile) {
+    case 16: launch_halo<16>(p, grid, false, s); break;
+    case 32: launch_halo<32>(p, grid, false, s); break;
+    case 64: launch_halo<64>(p, grid, false, s); break;
+    default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
+  }
+  RI_LAUNCH_CHECK();
+  return RI_OK;
 }
 
 }  // namespace ri

@@ -35,7 +35,6 @@ struct ri_pd_s {
   float* xt = nullptr;
   float* s = nullptr;
   float* st = nullptr;     // s~ = Psi s
-  float* g = nullptr;
   float2* sum = nullptr;   // sum_i M_i^dagger v~_i on the K x K grid
   double* eps = nullptr;   // d
   double* stats = nullptr; // d x 2
@@ -115,7 +114,6 @@ void destroy_pd(ri_pd_s* P) {
   dev_free(P->xt);
   dev_free(P->s);
   dev_free(P->st);
-  dev_free(P->g);
   dev_free(P->sum);
   dev_free(P->eps);
   dev_free(P->stats);
@@ -148,38 +146,6 @@ int sparsity_branch(ri_pd_s* P, hipStream_t s) {
   // step 13 (Moreau form of the soft-threshold), then step 14
   RI_STAGE(P, RI_STAGE_PSI_ADJ, s, psi_adj_apply(*P->sara, P->xt, P->s, true, P->alpha, s));
   RI_STAGE(P, RI_STAGE_PSI_SYNTH, s, psi_apply(*P->sara, P->s, P->st, s));
-  return RI_OK;
-}
-
-// Steps 17-18: x <- max(0, x - tau (sigma s~ + varsigma g)), x~ = 2 x_new - x_old.
-__global__ __launch_bounds__(256) void k_primal_update(const float4* __restrict__ st, const float4* __restrict__ g,
-                                                       float4* __restrict__ x, float4* __restrict__ xt, int n4,
-                                                       float tau, float sigma, float varsigma) {
-  for (int k = blockIdx.x * 256 + threadIdx.x; k < n4; k += gridDim.x * 256) {
-    const float4 a = st[k], b = g[k], xo = x[k];
-    float4 xn;
-    xn.x = fmaxf(0.f, xo.x - tau * (sigma * a.x + varsigma * b.x));
-    xn.y = fmaxf(0.f, xo.y - tau * (sigma * a.y + varsigma * b.y));
-    xn.z = fmaxf(0.f, xo.z - tau * (sigma * a.z + varsigma * b.z));
-    xn.w = fmaxf(0.f, xo.w - tau * (sigma * a.w + varsigma * b.w));
-    x[k] = xn;
-    xt[k] = make_float4(2.f * xn.x - xo.x, 2.f * xn.y - xo.y, 2.f * xn.z - xo.z, 2.f * xn.w - xo.w);
-  }
-}
-
-int primal_update_launch(ri_pd_s* P, hipStream_t s) {
-  const int n4 = P->plan->n * P->plan->n / 4;  // n >= 16
-  const int blocks = std::min((n4 + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_primal_update, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const float4*>(P->st),
-                     reinterpret_cast<const float4*>(P->g), reinterpret_cast<float4*>(P->x),
-                     reinterpret_cast<float4*>(P->xt), n4, float(P->prm.tau), float(P->prm.sigma),
-                     float(P->prm.varsigma));
-  RI_LAUNCH_CHECK();
-  return RI_OK;
-}
-
-int primal_update(ri_pd_s* P, hipStream_t s) {
-  RI_STAGE(P, RI_STAGE_UPDATE, s, primal_update_launch(P, s));
   return RI_OK;
 }
 
@@ -223,7 +189,6 @@ int ri_pd_create(ri_pd* out, ri_plan plan, ri_sara sara, const float* y, const d
   step(ri::dev_alloc(&P->xt, N));
   step(ri::dev_alloc(&P->s, size_t(S.b) * N));
   step(ri::dev_alloc(&P->st, N));
-  step(ri::dev_alloc(&P->g, N));
   step(ri::dev_alloc(&P->sum, KK));
   step(ri::dev_alloc(&P->eps, size_t(p.d)));
   step(ri::dev_alloc(&P->stats, 2 * size_t(p.d)));
@@ -245,7 +210,6 @@ int ri_pd_create(ri_pd* out, ri_plan plan, ri_sara sara, const float* y, const d
   step(rc == RI_OK ? ri::zero_f32(P->xt, N, stream) : rc);
   step(rc == RI_OK ? ri::zero_f32(P->s, size_t(S.b) * N, stream) : rc);
   step(rc == RI_OK ? ri::zero_f32(P->st, N, stream) : rc);
-  step(rc == RI_OK ? ri::zero_f32(P->g, N, stream) : rc);
   step(rc == RI_OK ? ri::zero_c64(P->sum, KK, stream) : rc);
   if (rc == RI_OK && hipStreamSynchronize(stream) != hipSuccess) rc = fail(RI_EHIP, "stream sync failed");
   if (rc != RI_OK) {
@@ -296,6 +260,12 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
   return RI_OK;
 }
 
+// The plain form differs from ri_pd_step only in the data term: one degridding and one
+// gridding launch per active block (over that block's own tiles) instead of one launch
+// over all active blocks; the halo rings of all blocks' launches are merged by one pass
+// after the last block.  Everything else (the sparsity branch forked after the forward
+// FFT, steps 17-18 fused into the adjoint row pass) is the same, so timing the two forms
+// against each other measures what batching the blocks gains.
 int ri_pd_step_plain(ri_pd P, const uint8_t* mask_host, double* stats, hipStream_t stream) {
   if (!P) return fail(RI_EINVAL, "pd is NULL");
   const ri::Plan& p = *P->plan;
@@ -307,6 +277,15 @@ int ri_pd_step_plain(ri_pd P, const uint8_t* mask_host, double* stats, hipStream
   RI_HIP(hipMemcpyAsync(P->mask_dev, mask_host, p.d, hipMemcpyHostToDevice, stream));
   RI_STAGE(P, RI_STAGE_FFT_ROWS, stream, ri::fft_forward_rows(p, P->xt, stream));
   RI_STAGE(P, RI_STAGE_FFT_COLS, stream, ri::fft_forward_cols(p, p.grid, stream));
+  const bool fork = !(P->timing && !ri::capturing(stream));
+  if (fork) {
+    RI_HIP(hipEventRecord(P->ev_fork, stream));
+    RI_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+    RI_TRY(ri::sparsity_branch(P, P->side));
+    RI_HIP(hipEventRecord(P->ev_join, P->side));
+  } else {
+    RI_TRY(ri::sparsity_branch(P, stream));
+  }
   RI_TRY(ri::stage_begin(P, RI_STAGE_DEGRID, stream));
   for (int i = 0; i < p.d; ++i) {
     if (!mask_host[i]) continue;
@@ -316,15 +295,17 @@ int ri_pd_step_plain(ri_pd P, const uint8_t* mask_host, double* stats, hipStream
   RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream,
            ri::block_stats(p, P->mask_dev, P->stats, stats, stream, P->eps, P->shrink));
   RI_TRY(ri::stage_begin(P, RI_STAGE_GRID, stream));
+  RI_TRY(ri::grid_blocks_begin(p, stream));
   for (int i = 0; i < p.d; ++i) {
     if (!mask_host[i]) continue;
     RI_TRY(ri::grid_project_block(p, i, P->e, P->v, P->shrink, P->sum, stream));
   }
   RI_TRY(ri::stage_end(P, RI_STAGE_GRID, stream));
+  RI_STAGE(P, RI_STAGE_GRID_HALO, stream, ri::grid_blocks_end(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
-  RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows(p, P->g, stream));
-  RI_TRY(ri::sparsity_branch(P, stream));
-  RI_TRY(ri::primal_update(P, stream));
+  if (fork) RI_HIP(hipStreamWaitEvent(stream, P->ev_join, 0));
+  const ri::PrimalUpdate upd{P->st, P->x, P->xt, float(P->prm.tau), float(P->prm.sigma), float(P->prm.varsigma)};
+  RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows_update(p, upd, stream));
   P->iter += 1;
   return RI_OK;
 }

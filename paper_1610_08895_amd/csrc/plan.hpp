@@ -88,11 +88,6 @@ struct Plan {
   float2* halo = nullptr;       // n_tiles * ring_cells(tile) halo rings of the gridding
   int n_empty = 0;
   int* empty_tiles = nullptr;   // n_empty tiles without visibilities
-  // The batched gridding rewrites the whole ring of every tile with visibilities in each
-  // launch, so its halo pass only reads the patches; the per-block gridding writes some
-  // tiles' patches only, so its halo pass clears what it reads, and the patches are
-  // zeroed first when a batched launch left them filled.
-  mutable bool halo_dirty = false;
   int* active_count = nullptr;
   float* norm_tmp = nullptr;  // n * n scratch for power iterations
   double* dsum = nullptr;     // FP64 reduction scratch
@@ -150,8 +145,13 @@ int grid_halo(const Plan& p, float2* grid, hipStream_t s);
 // y is complex interleaved (M), x real (n*n); both use the plan's work grid.
 int phi_apply(const Plan& p, const float* x, float* y, const uint8_t* mask, hipStream_t s);
 int phi_adj_apply(const Plan& p, const float* y, float* x, const uint8_t* mask, hipStream_t s);
+// Per-block form of grid_project: grid_blocks_begin zeroes the halo rings, each
+// grid_project_block adds one block's tile interiors into the grid and its rings into the
+// zeroed rings, and grid_blocks_end adds the rings into the grid (one halo pass).
+int grid_blocks_begin(const Plan& p, hipStream_t s);
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const float* shrink, float2* grid,
                        hipStream_t s);
+int grid_blocks_end(const Plan& p, float2* grid, hipStream_t s);
 // grid = G^dagger v over all items (rebuilds the running sum from scratch).
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s);
 

@@ -274,6 +274,50 @@ class PD:
             pass
 
 
+class DeviceSchedule:
+    """Buffers of the device-side block selection (ri_sched_step) for T iterations.
+
+    Exactly one of u (T x d uniforms, drawn against the probabilities) or masks (T x d,
+    replayed) is given.  p_fixed: d probabilities of a non-adaptive schedule (None: 1).
+    c0: the Eq. 13 energies at the start of an adaptive run.  stats_step, stats_x: the
+    (d, 2) FP64 device tensors that ri_pd_step and ri_pd_residual write.  The mask tensor
+    is what the step reads; p_log and mask_log keep every iteration's probabilities and
+    mask on the device until read back.
+    """
+
+    def __init__(self, d, T, eps, stats_step, stats_x=None, u=None, masks=None, p_fixed=None, c0=None,
+                 n_nodes=0.0, p_min=0.05, p_max=0.5):
+        if (u is None) == (masks is None):
+            raise ValueError("give exactly one of u and masks")
+        dev = "cuda"
+        self.d, self.T = int(d), int(T)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.u = None if u is None else torch.tensor(np.asarray(u, np.float64).reshape(T, d), **f64)
+        self.masks = None if masks is None else torch.tensor(np.asarray(masks, np.uint8).reshape(T, d),
+                                                              dtype=torch.uint8, device=dev)
+        self.p_fixed = None if p_fixed is None else torch.tensor(np.asarray(p_fixed, np.float64).reshape(d), **f64)
+        self.c = torch.tensor(np.zeros(d) if c0 is None else np.asarray(c0, np.float64).reshape(d), **f64)
+        self.eps = torch.tensor(np.asarray(eps, np.float64).reshape(d), **f64)
+        self.counter = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.mask = torch.ones(d, dtype=torch.uint8, device=dev)
+        self.p_log = torch.zeros(T, d, **f64)
+        self.mask_log = torch.zeros(T, d, dtype=torch.uint8, device=dev)
+        _dev(stats_step, torch.float64, (d, 2), "stats_step")
+        if stats_x is not None:
+            _dev(stats_x, torch.float64, (d, 2), "stats_x")
+        self.stats_step, self.stats_x = stats_step, stats_x
+
+        def ptr(t):
+            return None if t is None else t.data_ptr()
+
+        self._a = L.Sched(self.d, self.T, ptr(self.u), ptr(self.masks), ptr(self.p_fixed), ptr(self.c),
+                          ptr(stats_step), ptr(stats_x), ptr(self.eps), float(n_nodes), float(p_min),
+                          float(p_max), ptr(self.counter), ptr(self.mask), ptr(self.p_log), ptr(self.mask_log))
+
+    def step(self, flags):
+        L.check(L.load().ri_sched_step(ctypes.byref(self._a), int(flags), _stream()))
+
+
 def residual_energy(resid_norm, eps):
     """Eq. 13 (host, in the library)."""
     r = np.ascontiguousarray(resid_norm, dtype=np.float64)

@@ -1,10 +1,11 @@
 """Host control flow of Algorithm 1: block selection (step 3), step sizes, the adaptive
 probabilities of Sec. IV, and iteration of the GPU step.
 
-Everything numeric inside an iteration runs in libri.so.  The host only turns uniform
-variates into the active set (block i is active when u[t, i] < p_i, Sec. III-B: each
-block independently with probability p_i), evaluates Eqs. 13-14 through the library's
-host entry points, and moves the d-byte mask and the d x 2 block statistics.
+Everything numeric inside an iteration runs in libri.so, including the block selection of
+the batched form: block i is active when u[t, i] < p_i (Sec. III-B: each block
+independently with probability p_i), with p from Eqs. 13-14 for the adaptive schedule,
+drawn on the device from uniforms uploaded once (ri_sched_step).  The host only decides
+which captured graph to replay.  The plain per-block form draws on the host.
 """
 import dataclasses
 import math
@@ -12,7 +13,8 @@ import math
 import numpy as np
 import torch
 
-from .ops import PD, Plan, Sara, probabilities, residual_energy
+from ._lib import SCHED_ADAPTIVE, SCHED_DRAW, SCHED_REFRESH, SCHED_UPDATE
+from .ops import PD, DeviceSchedule, Plan, Sara, probabilities, residual_energy
 
 
 @dataclasses.dataclass
@@ -49,7 +51,9 @@ class Solver:
         self.eps = np.asarray(eps, dtype=np.float64)
         self.y_plan = y_plan
         self.mask_dev = torch.ones(plan.d, dtype=torch.uint8, device="cuda")
+        self._mask_host = np.ones(plan.d, np.uint8)  # what mask_dev holds
         self.stats_dev = torch.zeros(plan.d, 2, dtype=torch.float64, device="cuda")
+        self.res_dev = torch.zeros(plan.d, 2, dtype=torch.float64, device="cuda")
         self._graph = None
 
     def initial_energy(self):
@@ -62,26 +66,33 @@ class Solver:
         sq = self.pd.residual().cpu().numpy()[:, 1]
         return residual_energy(np.sqrt(sq), self.eps)
 
-    def capture(self):
-        """Capture one iteration (reading self.mask_dev) into a graph for replay."""
+    def _capture(self, fn):
+        """Capture the kernels fn enqueues (without running them) into a graph."""
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         g = torch.cuda.CUDAGraph()
-        it = self.pd.iteration   # capture records the kernels without running them
+        it = self.pd.iteration   # the library counts the captured step; restore it
         with torch.cuda.graph(g, stream=s):
-            self.pd.step(self.mask_dev, self.stats_dev)
+            fn()
         torch.cuda.current_stream().wait_stream(s)
         self.pd.iteration = it
-        self._graph = g
         return g
 
+    def capture(self):
+        """Capture one iteration (reading self.mask_dev) into a graph for replay."""
+        self._graph = self._capture(lambda: self.pd.step(self.mask_dev, self.stats_dev))
+        return self._graph
+
+    def _set_mask(self, mask_host):
+        m = np.ones(self.plan.d, np.uint8) if mask_host is None else np.ascontiguousarray(mask_host, np.uint8)
+        if not np.array_equal(m, self._mask_host):  # a copy only when the mask changes
+            self.mask_dev.copy_(torch.from_numpy(m.copy()))
+            self._mask_host = m.copy()
+
     def step(self, mask_host=None, graph=False, plain=False):
-        if mask_host is not None:
-            self.mask_dev.copy_(torch.from_numpy(np.ascontiguousarray(mask_host, dtype=np.uint8)))
-        else:
-            self.mask_dev.fill_(1)
+        self._set_mask(mask_host)
         if plain:
-            self.pd.step_plain(mask_host, self.stats_dev)
+            self.pd.step_plain(self._mask_host, self.stats_dev)
         elif graph:
             if self._graph is None:
                 self.capture()
@@ -90,36 +101,59 @@ class Solver:
         else:
             self.pd.step(self.mask_dev, self.stats_dev)
 
+    def prepare(self, iterations, schedule: Schedule = Schedule(), uniforms=None, masks=None, graph=False,
+                seed=0):
+        """A batched run of `iterations` steps, prepared but not started (see `run`): call
+        its step() once per iteration, then history().  Nothing syncs with the host between
+        steps."""
+        return BatchedRun(self, iterations, schedule, uniforms, masks, graph, seed)
+
     def run(self, iterations, schedule: Schedule = Schedule(), uniforms=None, masks=None, refresh=64,
-            x_true=None, snr_every=0, graph=False, plain=False, callback=None):
+            x_true=None, snr_every=0, graph=False, plain=False, callback=None, seed=0):
         """Run `iterations` steps.  Masks come from `masks` (replayed), else from
-        `uniforms` (T x d) against the schedule's probabilities; with masks replayed, an
-        adaptive schedule's probabilities are still computed and logged.  `refresh` rebuilds
-        the running sum of G_i^dagger v_i every that many steps.  Returns a history dict."""
+        `uniforms` (T x d) against the schedule's probabilities, else from uniforms drawn
+        here with np.random.default_rng(seed) (only p = 1 without either runs every block
+        without drawing); with masks replayed, an adaptive schedule's probabilities are
+        still computed and logged.  The batched form selects blocks on the device
+        (ri_sched_step), so iterations follow each other without a host round trip; the
+        plain form (per-block launches, which need the mask on the host) selects them on
+        the host.  `refresh` rebuilds the running sum of G_i^dagger v_i every that many
+        steps.  Returns a history dict (masks and probabilities per iteration, SNR)."""
+        if plain:
+            T = int(iterations)
+            p_fixed, uniforms, masks, _ = _draws(self.plan.d, T, schedule, uniforms, masks, seed)
+            return self._run_host(T, schedule, p_fixed, uniforms, masks, refresh, x_true, snr_every, callback)
+        r = self.prepare(iterations, schedule, uniforms, masks, graph, seed)
+        snrs = []
+        for t in range(r.T):
+            r.step()
+            if refresh and (t + 1) % refresh == 0:
+                self.pd.refresh()
+            if x_true is not None and snr_every and ((t + 1) % snr_every == 0 or t + 1 == r.T):
+                snrs.append((t + 1, snr(x_true, self.x())))
+            if callback is not None:
+                callback(t, self)
+        h = r.history()
+        h["snr"] = snrs
+        return h
+
+    def _run_host(self, T, schedule, p_fixed, uniforms, masks, refresh, x_true, snr_every, callback):
+        """The plain form's loop: blocks drawn on the host, one step at a time."""
         d = self.plan.d
-        adaptive = schedule.kind == "adaptive"
+        adaptive = p_fixed is None
         c = self.initial_energy() if adaptive else None
-        if schedule.kind == "fixed":
-            p_fixed = np.asarray(schedule.p_vec, dtype=np.float64)
-            if p_fixed.shape != (d,) or np.any(p_fixed < 0) or np.any(p_fixed > 1):
-                raise ValueError("p_vec must hold d probabilities in [0, 1]")
-        elif schedule.kind not in ("uniform", "adaptive"):
-            raise ValueError(f"unknown schedule kind {schedule.kind!r}")
         hist = {"masks": [], "p": [], "snr": []}
-        for t in range(iterations):
+        for t in range(T):
             if adaptive and schedule.refresh_every and t > 0 and t % schedule.refresh_every == 0:
                 c = self.energy()
-            if adaptive:
-                p, _ = probabilities(c, schedule.n_nodes, schedule.p_min, schedule.p_max)
-            elif schedule.kind == "fixed":
-                p = p_fixed
-            else:
-                p = np.full(d, schedule.p)
+            p = probabilities(c, schedule.n_nodes, schedule.p_min, schedule.p_max)[0] if adaptive else p_fixed
             if masks is not None:
-                mask = np.asarray(masks[t], dtype=np.uint8)
+                mask = masks[t]
+            elif uniforms is not None:
+                mask = (uniforms[t] < p).astype(np.uint8)
             else:
-                mask = (uniforms[t] < p).astype(np.uint8) if uniforms is not None else np.ones(d, np.uint8)
-            self.step(mask, graph=graph, plain=plain)
+                mask = np.ones(d, np.uint8)
+            self.step(mask, plain=True)
             if adaptive:
                 st = self.stats_dev.cpu().numpy()
                 act = np.flatnonzero(mask)
@@ -129,7 +163,7 @@ class Solver:
                 self.pd.refresh()
             hist["masks"].append(mask)
             hist["p"].append(p)
-            if x_true is not None and snr_every and ((t + 1) % snr_every == 0 or t + 1 == iterations):
+            if x_true is not None and snr_every and ((t + 1) % snr_every == 0 or t + 1 == T):
                 hist["snr"].append((t + 1, snr(x_true, self.x())))
             if callback is not None:
                 callback(t, self)
@@ -137,6 +171,91 @@ class Solver:
 
     def x(self):
         return self.pd.get(0).cpu().numpy().astype(np.float64)
+
+
+def _draws(d, T, schedule, uniforms, masks, seed):
+    """(p_fixed or None for adaptive, uniforms, masks, every_block) of a run."""
+    if schedule.kind == "fixed":
+        p_fixed = np.asarray(schedule.p_vec, dtype=np.float64)
+        if p_fixed.shape != (d,) or np.any(p_fixed < 0) or np.any(p_fixed > 1):
+            raise ValueError("p_vec must hold d probabilities in [0, 1]")
+    elif schedule.kind == "uniform":
+        p_fixed = np.full(d, float(schedule.p))
+    elif schedule.kind == "adaptive":
+        p_fixed = None
+    else:
+        raise ValueError(f"unknown schedule kind {schedule.kind!r}")
+    every_block = masks is None and uniforms is None and p_fixed is not None and bool(np.all(p_fixed >= 1.0))
+    if masks is None and uniforms is None and not every_block:
+        uniforms = np.random.default_rng(seed).random((T, d))
+    if masks is not None:
+        masks = np.asarray(masks, dtype=np.uint8)[:T]
+        if masks.shape != (T, d):
+            raise ValueError(f"masks must be ({T}, {d})")
+    if uniforms is not None:
+        uniforms = np.asarray(uniforms, dtype=np.float64)[:T]
+        if uniforms.shape != (T, d):
+            raise ValueError(f"uniforms must be ({T}, {d})")
+    return p_fixed, uniforms, masks, every_block
+
+
+class BatchedRun:
+    """Iterations of the batched step with the block selection on the device.
+
+    Each step() enqueues the draw of iteration t (ri_sched_step: Eq. 13 update from the
+    last step's statistics and Eq. 14 for the adaptive schedule, then u[t, i] < p_i, or the
+    replayed mask) and the step reading that mask; with refresh_every = K the draw of every
+    K-th iteration is preceded by Eq. 13 at x for all blocks (ri_pd_residual).  With
+    graph=True the two sequences are captured once each and replayed."""
+
+    def __init__(self, solver, iterations, schedule, uniforms, masks, graph, seed):
+        self.sol, self.T, self.graph = solver, int(iterations), graph
+        d = solver.plan.d
+        p_fixed, uniforms, masks, every_block = _draws(d, self.T, schedule, uniforms, masks, seed)
+        adaptive = p_fixed is None
+        self.K = schedule.refresh_every if adaptive else 0
+        self.sched = None
+        if not every_block:
+            self.sched = DeviceSchedule(d, self.T, solver.eps, solver.stats_dev, solver.res_dev,
+                                        u=uniforms if masks is None else None, masks=masks, p_fixed=p_fixed,
+                                        c0=solver.initial_energy() if adaptive else None, n_nodes=schedule.n_nodes,
+                                        p_min=schedule.p_min, p_max=schedule.p_max)
+        self.mask = self.sched.mask if self.sched is not None else torch.ones(d, dtype=torch.uint8, device="cuda")
+        self.flags = SCHED_DRAW | ((SCHED_UPDATE | SCHED_ADAPTIVE) if adaptive else 0)
+        if self.K:
+            solver.pd.residual(solver.res_dev)  # its scratch is allocated outside any capture
+        self.graphs = {}
+        self.t = 0
+
+    def _body(self):
+        if self.sched is not None:
+            self.sched.step(self.flags)
+        self.sol.pd.step(self.mask, self.sol.stats_dev)
+
+    def _body_refresh(self):  # Eq. 13 recomputed for every block at x before the draw
+        self.sol.pd.residual(self.sol.res_dev)
+        self.sched.step(SCHED_REFRESH | SCHED_ADAPTIVE | SCHED_DRAW)
+        self.sol.pd.step(self.mask, self.sol.stats_dev)
+
+    def step(self):
+        exact = bool(self.K) and self.t > 0 and self.t % self.K == 0
+        fn = self._body_refresh if exact else self._body
+        if self.graph:
+            if exact not in self.graphs:
+                self.graphs[exact] = self.sol._capture(fn)
+            self.graphs[exact].replay()
+            self.sol.pd.iteration = self.sol.pd.iteration + 1
+        else:
+            fn()
+        self.t += 1
+
+    def history(self):
+        """Masks and probabilities of the iterations run so far (one copy to the host)."""
+        d = self.sol.plan.d
+        if self.sched is None:
+            return {"masks": list(np.ones((self.t, d), np.uint8)), "p": list(np.ones((self.t, d)))}
+        return {"masks": list(self.sched.mask_log.cpu().numpy()[:self.t]),
+                "p": list(self.sched.p_log.cpu().numpy()[:self.t])}
 
 
 def snr(x_true, x_hat):

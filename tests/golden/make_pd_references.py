@@ -5,9 +5,15 @@ the noise level, the l2-ball radii, ||Phi|| from a fixed number of power iterati
 SNR trajectory, and for randomised schedules the block masks the oracle drew, so that the
 GPU run can replay them.
 
-    python tests/golden/make_pd_references.py n256_m128k_d16     # both schedules, 500 iterations
-    python tests/golden/make_pd_references.py n1024_m4m_d64 100  # p = 1, first 100 iterations
+    python tests/golden/make_pd_references.py n256_m128k_d16                  # both schedules, 500 it
+    python tests/golden/make_pd_references.py n1024_m4m_d64 200 p1            # p = 1, 200 iterations
+    python tests/golden/make_pd_references.py n1024_m4m_d64 200 adaptive16    # Eq. 14, sum p = 16
+
+With labels given, only those schedules run, and their records are merged into the
+workload's file (under a lock, so several labels can run as separate processes); each
+record carries its own iteration count.
 """
+import fcntl
 import json
 import os
 import sys
@@ -33,7 +39,7 @@ def pack_masks(masks):
     return ["".join("1" if b else "0" for b in row) for row in np.asarray(masks, bool)]
 
 
-def main(name, iterations=None):
+def main(name, iterations=None, labels=None):
     w = synth.WORKLOADS[name]
     T = iterations or w.iterations
     inp = synth.make_inputs(w)
@@ -46,8 +52,10 @@ def main(name, iterations=None):
     print(f"{name}: setup {time.time() - t0:.0f}s ||Phi||={fn:.6f}", flush=True)
     runs = {}
     for label, kind, kw in w.prob_schemes:
+        if labels and label not in labels:
+            continue
         t1 = time.time()
-        rec = {"kind": kind, "params": kw, "snr": []}
+        rec = {"kind": kind, "params": kw, "snr": [], "iterations": T}
         every = 10
 
         def cb(st, stats, r):
@@ -71,20 +79,27 @@ def main(name, iterations=None):
             rec["masks"] = pack_masks(masks)
             rec["p_first"] = probs[0].tolist()
         runs[label] = rec
-        if kind == "uniform" and kw["p"] >= 1.0:
-            pass
-        if name == "n1024_m4m_d64":
-            break  # the p = 1 run only: the 1024^2 oracle costs tens of seconds per iteration
     out = {
         "_source": "written by tests/golden/make_pd_references.py from the FP64 oracle (oracle/) and synth",
         "workload": name, "iterations": T, "sigma_n": sig, "eps": eps.tolist(), "phi_norm": fn,
         "power_iterations": POWER_ITERS, "psi_norm": 3.0, "tau": prm.tau, "kappa": prm.kappa, "runs": runs,
     }
     path = os.path.join(OUT, f"pd_reference_{name}.json")
-    with open(path, "w") as f:
-        json.dump(out, f)
+    with open(path + ".lock", "w") as lk:
+        fcntl.flock(lk, fcntl.LOCK_EX)
+        if labels and os.path.exists(path):
+            with open(path) as f:
+                old = json.load(f)
+            for k in ("sigma_n", "phi_norm"):
+                assert abs(old[k] - out[k]) <= 1e-12 * abs(out[k]), f"{k} differs from the stored file"
+            old["runs"].update(runs)
+            old["iterations"] = max(r.get("iterations", old["iterations"]) for r in old["runs"].values())
+            out = old
+        with open(path, "w") as f:
+            json.dump(out, f)
+    os.remove(path + ".lock")
     print("wrote", path, flush=True)
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else None)
+    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else None, sys.argv[3:] or None)
