@@ -122,13 +122,14 @@ def make_problem(w, R, tune, phi_iters=50):
     return dict(inp=inp, plan=plan, x_true=x_true, y_user=y_user, y_plan=y_plan, eps=eps, phi_norm=phi_norm)
 
 
-def time_run(sol, schedule, warmup, steps, refresh=64, seed=0):
+def time_run(sol, schedule, warmup, steps, refresh=64, seed=0, reweight=None):
     """ms per iteration of graph-replayed batched steps with the device-side block selection,
-    the running-sum refresh every `refresh` iterations inside the timed region, and the mean
-    number of active blocks and visibilities per timed iteration."""
+    the running-sum refresh every `refresh` iterations (and the reweighting, if any) inside
+    the timed region, and the mean number of active blocks and visibilities per timed
+    iteration."""
     import torch
 
-    r = sol.prepare(warmup + steps, schedule, graph=True, seed=seed)
+    r = sol.prepare(warmup + steps, schedule, graph=True, seed=seed, reweight=reweight)
     for t in range(warmup):
         r.step()
         if refresh and (t + 1) % refresh == 0:
@@ -310,6 +311,16 @@ def main():
             "mean_active_vis": round(nv_a), "active_gvis_s": round(nv_a / ms_a / 1e6, 2)}
         log(f"adaptive16: {ms_a:.4f} ms/iter, {nb_a:.1f} blocks / {nv_a / 1e6:.2f} M vis active")
         del sol_a
+        # reweighted SARA: weighted clip bounds in every step, weights refreshed every 50
+        from paper_1610_08895_amd.solver import Reweight
+
+        sol_r = Solver(plan, sara, y_plan, eps, psi_norm, phi_norm)
+        ms_r, _, _ = time_run(sol_r, Schedule(), args.warmup, args.steps, reweight=Reweight(50, 1e-2, 0.5))
+        extra["reweighted"] = {"schedule": "p = 1, weights w = delta / (delta + |Psi^dagger x|) every 50 "
+                                           "iterations (delta 1e-2 halving)",
+                               "iters_s": round(1e3 / ms_r, 2), "ms_per_step": round(ms_r, 5)}
+        log(f"reweighted: {ms_r:.4f} ms/iter")
+        del sol_r
 
     # ---- CPU oracle baseline: one iteration of Algorithm 1 on the same workload ----
     cpu = None

@@ -100,6 +100,22 @@ int ri_plan_order(ri_plan plan, int64_t* order_host);
  * to_plan != 0: dst[k] = src[order[k]]; else dst[order[k]] = src[k].  src != dst. */
 int ri_plan_permute(ri_plan plan, const float* src, float* dst, int to_plan, hipStream_t stream);
 
+/*
+ * Direction-dependent effects in G (Eq. 1's D(l, u), which Sec. II folds into the kernels
+ * of G).  The DDE of visibility m is band limited on the oversampled grid,
+ * D_m(l) = sum_{p,q=-h..h} d_m[q][p] exp(-2 pi i (p l_x + q l_y) / K), so its row of G becomes
+ * the jd x jd kernel d_m convolved with the Kaiser-Bessel kernel: (8 + 2h)^2 complex weights
+ * per visibility, built on the device by this call and stored (S^2 * 8 bytes per
+ * visibility, S = 8 + 2h).  From then on ri_phi, ri_phi_adj, ri_phi_norm and the Algorithm 1
+ * steps of solvers on this plan use the DDE-aware G (the adjoint with conjugate weights).
+ * d_host: M * jd * jd complex float32 (host, user order of the visibilities; per
+ * visibility row-major [q + h][p + h], q along v / rows, p along u / columns).
+ * jd odd, 1 <= jd <= 7; jd = 0 with d_host = NULL removes the DDEs (plain G again).
+ * Synchronises `stream`.  A graph captured before the call keeps the G it was captured with.
+ * Errors: RI_EINVAL (NULL plan, jd out of range, non-finite taps), RI_ENOMEM, RI_EHIP.
+ */
+int ri_plan_dde(ri_plan plan, int jd, const float* d_host, hipStream_t stream);
+
 /* y_i = Phi_i x for every block i with mask[i] != 0 (Algorithm 1 steps 4-5 and G_i b_i).
  * x: device n*n float32; y: device M complex (plan order); rows of inactive blocks are
  * left untouched.  mask: device d uint8 or NULL. */
@@ -234,13 +250,32 @@ enum {
   RI_PD_S = 2,     /* b*n*n float32                                 */
   RI_PD_V = 3,     /* M complex float32, plan order                 */
   RI_PD_ITER = 4,  /* int64 iteration counter (host buffer)         */
-  RI_PD_E = 5      /* M complex float32: G_i b_i - y_i of the last step's active blocks
+  RI_PD_E = 5,     /* M complex float32: G_i b_i - y_i of the last step's active blocks
                       (read only)                                   */
+  RI_PD_W = 6      /* b*n*n float32 weights w_k of the weighted l1 prior (layout of S);
+                      set allocates them on first use, set with buf = NULL and bytes = 0
+                      returns to the plain prior; get fails with RI_ESTATE without them */
 };
 /* Copy state `which` to/from buf (device, or host for RI_PD_ITER), `bytes` long.
  * ri_pd_set recomputes sum_i M_i^dagger v~_i from the stored v when V is set. */
 int ri_pd_get(ri_pd pd, int which, void* buf, size_t bytes, hipStream_t stream);
 int ri_pd_set(ri_pd pd, int which, const void* buf, size_t bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------------------
+ * Reweighted SARA (the SARA prior the paper cites, Sec. II-III): the weighted analysis
+ * prior ||W Psi^dagger x||_1, W = diag(w), whose proximity operator thresholds each
+ * coefficient at alpha w_k, so step 13 becomes s = clip(s + Psi^dagger x~, -alpha w, alpha w).
+ * ------------------------------------------------------------------------------------ */
+
+/* w_k = delta / (delta + |[Psi^dagger x]_k|) from the current primal iterate x (the
+ * derivative of the log penalty delta log(delta + |c|), which the weighted l1 norm
+ * majorises), stored as RI_PD_W; every later step uses them.  The first call (or the first
+ * set of RI_PD_W) allocates b*n*n floats, initialised to 1; later calls only enqueue.  A
+ * graph captured before the weights existed keeps the plain prior.
+ * Errors: RI_EINVAL (NULL pd, delta not positive and finite), RI_ENOMEM, RI_EHIP. */
+int ri_pd_reweight(ri_pd pd, double delta, hipStream_t stream);
+/* *out = 1 if the solver uses weights (RI_PD_W), else 0 (host output). */
+int ri_pd_weighted(ri_pd pd, int* out);
 
 /* ------------------------------------------------------------------------------------
  * Differentiation of unrolled iterations (masks fixed; the map (tau, sigma) -> x is then

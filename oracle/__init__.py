@@ -10,6 +10,7 @@ the only thing both sides share is the seeded input generator (``synth``).
 Contents, each citing the passage it follows:
   kaiser_bessel  interpolation kernel and its Fourier transform (Eq. 3's G and Z)
   measurement    Phi = G M F Z per data block, its adjoint, and a direct NUDFT (Eqs. 2, 3, 8)
+  dde            DDE-aware G (Eq. 1's D folded into G's kernels, Sec. II) and its direct NUDFT
   wavelets       Daubechies filters and the SARA dictionary Psi (Sec. III)
   prox           Eqs. 10, 11, 12 and the Moreau forms of Algorithm 1 steps 8 and 13
   probs          Eqs. 13 and 14

@@ -12,7 +12,7 @@ import torch  # noqa: F401  (must precede the library load, see above)
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libri.so")
 
 RI_OK, RI_EINVAL, RI_ENOMEM, RI_EHIP, RI_ESTATE = 0, -1, -2, -3, -4
-RI_PD_X, RI_PD_XTILDE, RI_PD_S, RI_PD_V, RI_PD_ITER, RI_PD_E = range(6)
+RI_PD_X, RI_PD_XTILDE, RI_PD_S, RI_PD_V, RI_PD_ITER, RI_PD_E, RI_PD_W = range(7)
 STAGES = ("fft_rows", "fft_cols", "degrid", "block_norms", "grid", "grid_halo", "ifft_cols", "ifft_rows",
           "psi_adj", "psi_synth", "update")
 
@@ -76,6 +76,9 @@ SIGNATURES = {
     "ri_residual_energy": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
     "ri_probs": (c_int, [c_void_p, c_int, c_double, c_double, c_double, c_void_p, P(c_double)]),
     "ri_sched_step": (c_int, [P(Sched), c_int, c_void_p]),
+    "ri_pd_reweight": (c_int, [c_void_p, c_double, c_void_p]),
+    "ri_plan_dde": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+    "ri_pd_weighted": (c_int, [c_void_p, P(c_int)]),
 }
 
 _lib = None

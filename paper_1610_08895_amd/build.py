@@ -36,8 +36,10 @@ COMMON = [
 
 # Per-source extra flags.  The gridding kernels round with floor(fma(w, t, c)), which becomes
 # one v_cvt_flr_i32_f32 only when NaN and infinity need not be honoured; every value they
-# round is finite.
-EXTRA = {"gridding.hip": ["-fno-honor-nans", "-fno-honor-infinities"]}
+# round is finite.  Later flags override COMMON's.
+EXTRA = {"gridding.hip": ["-fno-honor-nans", "-fno-honor-infinities"],
+         # the DDE kernels round the same way, and dispatch through templated lambdas (C++20)
+         "dde.hip": ["-fno-honor-nans", "-fno-honor-infinities", "-std=c++20"]}
 
 
 def _compile(src, verbose):

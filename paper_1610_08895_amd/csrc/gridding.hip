@@ -40,24 +40,6 @@ constexpr int GT = 256;    // threads per workgroup
 static_assert(GT / 64 == PART_WAVES, "one norm partial per wavefront of a workgroup");
 constexpr int GGT = 256;  // threads per workgroup of the tile gridding
 
-__device__ __forceinline__ void kb_weights(unsigned packed, const KBPoly& P, float* w, int& cell) {
-  cell = int(packed >> FRAC_BITS);
-  const float f = float(packed & FRAC_MASK) * (1.0f / float(1u << FRAC_BITS));
-  const float x = 2.0f * f - 1.0f;
-  const float x2 = x * x;
-#pragma unroll
-  for (int j = 0; j < KB_J / 2; ++j) {
-    float e = P.e[j][KB_HALF_DEG], o = P.o[j][KB_HALF_DEG];
-#pragma unroll
-    for (int k = KB_HALF_DEG - 1; k >= 0; --k) {
-      e = fmaf(e, x2, P.e[j][k]);
-      o = fmaf(o, x2, P.o[j][k]);
-    }
-    w[j] = fmaf(x, o, e);
-    w[KB_J - 1 - j] = fmaf(-x, o, e);
-  }
-}
-
 // Items base .. base + count - 1.
 struct ItemSource {
   const Item* items;
@@ -65,7 +47,7 @@ struct ItemSource {
 };
 
 
-enum { DG_APPLY = 0, DG_RESIDUAL = 1 };
+enum { DG_APPLY = 0, DG_RESIDUAL = 1, DG_NORMS = 2 };  // NORMS: the residual's norms only
 
 // LDS row pitch of a staged tile: one more than the region width, so that rows of the
 // tile start in different LDS banks.
@@ -129,7 +111,7 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
         const int s = threadIdx.x + k * GT;
         if (s < it.w) {
           c[k] = coord[it.z + s];
-          if (MODE == DG_RESIDUAL) {
+          if (MODE != DG_APPLY) {
             yy[k] = y[it.z + s];
             vv[k] = v[it.z + s];
           }
@@ -164,13 +146,13 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
           } else {
             const float2 e = make_float2(acc.x - yy[k].x, acc.y - yy[k].y);
             const float2 r = make_float2(vv[k].x + e.x, vv[k].y + e.y);
-            out[it.z + s] = e;
+            if (MODE == DG_RESIDUAL) out[it.z + s] = e;
             sr += double(r.x) * r.x + double(r.y) * r.y;
             se += double(e.x) * e.x + double(e.y) * e.y;
           }
         }
       }
-      if (MODE == DG_RESIDUAL) {
+      if (MODE != DG_APPLY) {
         sr = wave_sum(sr);
         se = wave_sum(se);
         if (lane == 0) {
@@ -652,9 +634,6 @@ int grid_units(const Plan& p, bool sliced, const int4* units, int nunits, const 
 
 }  // namespace
 
-int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s, const double* eps,
-                float* shrink);
-
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s) {
   ItemSource src{p.items, 0, p.n_items};
   hipLaunchKernelGGL(k_block_sumsq, dim3(wgs_for(p, p.n_items)), dim3(GT), 0, s, src, y, p.item_part);
@@ -666,15 +645,16 @@ int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s) {
 }
 
 int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s, const double* eps,
-                float* shrink) {
+                float* shrink, const double* part) {
   if ((eps == nullptr) != (shrink == nullptr)) return fail(RI_EINVAL, "block_stats: eps and shrink go together");
-  hipLaunchKernelGGL(k_block_stats, dim3(p.d), dim3(GT), 0, s, mask, p.item_off, p.item_part, stats, out, eps,
-                     shrink);
+  hipLaunchKernelGGL(k_block_stats, dim3(p.d), dim3(GT), 0, s, mask, p.item_off, part ? part : p.item_part, stats,
+                     out, eps, shrink);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }
 
 int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* mask, hipStream_t s) {
+  if (p.dde.on()) return dde_degrid(p, p.dunits, p.n_dunits, p.titems, mask, grid, y, nullptr, nullptr, nullptr, s);
   const dim3 grid_dim(wgs_for(p, p.n_dunits));
 #define ARGS p.dunits, p.n_dunits, p.titems, mask, p.coord, grid, p.K, p.tpa, p.poly, y, \
              (const float2*)nullptr, (const float2*)nullptr, (double*)nullptr
@@ -686,6 +666,7 @@ int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* ma
 
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
                     const uint8_t* mask, hipStream_t s) {
+  if (p.dde.on()) return dde_degrid(p, p.dunits, p.n_dunits, p.titems, mask, grid, e, y, v, p.item_part, s);
   const dim3 grid_dim(wgs_for(p, p.n_dunits));
 #define ARGS p.dunits, p.n_dunits, p.titems, mask, p.coord, grid, p.K, p.tpa, p.poly, e, y, v, \
              p.item_part
@@ -695,9 +676,21 @@ int degrid_residual(const Plan& p, const float2* grid, const float2* y, const fl
   return RI_OK;
 }
 
+int degrid_norms(const Plan& p, const float2* grid, const float2* y, const float2* v, double* part, hipStream_t s) {
+  if (p.dde.on()) return dde_degrid(p, p.dunits, p.n_dunits, p.titems, nullptr, grid, nullptr, y, v, part, s);
+  const dim3 grid_dim(wgs_for(p, p.n_dunits));
+#define ARGS p.dunits, p.n_dunits, p.titems, (const uint8_t*)nullptr, p.coord, grid, p.K, p.tpa, p.poly, \
+             (float2*)nullptr, y, v, part
+  RI_TILE_DISPATCH(k_degrid, DG_NORMS)
+#undef ARGS
+  RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
 int degrid_residual_block(const Plan& p, int block, const float2* grid, const float2* y, const float2* v,
                           float2* e, hipStream_t s) {
   const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
+  if (p.dde.on()) return dde_degrid(p, p.bunits + a, b - a, p.items, nullptr, grid, e, y, v, p.item_part, s);
   const dim3 grid_dim(wgs_for(p, b - a));
 #define ARGS p.bunits + a, b - a, p.items, (const uint8_t*)nullptr, p.coord, grid, p.K, p.tpa, p.poly, e, \
              y, v, p.item_part
@@ -708,22 +701,30 @@ int degrid_residual_block(const Plan& p, int block, const float2* grid, const fl
 }
 
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s) {
+  if (p.dde.on()) {
+    RI_TRY(dde_grid(p, p.dde.tunits, p.dde.n_tunits, p.titems, mask, y, nullptr, nullptr, nullptr, false, false, s));
+    return dde_merge(p, grid, false, s);
+  }
   return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.titems, mask, grid, y, nullptr, nullptr, nullptr,
                               s, true, true);
 }
 
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s) {
+  if (p.dde.on()) return grid_apply(p, v, nullptr, grid, s);
   return grid_units<GR_APPLY>(p, true, p.units, p.n_units, p.titems, nullptr, grid, v, nullptr, nullptr,
                               nullptr, s, true, true);
 }
 
 int grid_project(const Plan& p, const float2* e, float2* v, const float* shrink, const uint8_t* mask, float2* grid,
                  hipStream_t s) {
+  if (p.dde.on())  // the tiles' patches; grid_halo adds them into the grid
+    return dde_grid(p, p.dde.tunits, p.dde.n_tunits, p.titems, mask, nullptr, e, v, shrink, true, false, s);
   return grid_units<GR_PROJECT>(p, true, p.units, p.n_units, p.titems, mask, grid, nullptr, e, v, shrink, s,
                                 false);
 }
 
 int grid_halo(const Plan& p, float2* grid, hipStream_t s) {
+  if (p.dde.on()) return dde_merge(p, grid, true, s);
   switch (p.tile) {
     case 16: launch_halo<16>(p, grid, true, s); break;
     case 32: launch_halo<32>(p, grid, true, s); break;
@@ -737,15 +738,18 @@ int grid_halo(const Plan& p, float2* grid, hipStream_t s) {
 int grid_project_block(const Plan& p, int block, const float2* e, float2* v, const float* shrink, float2* grid,
                        hipStream_t s) {
   const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
+  if (p.dde.on()) return dde_grid(p, p.bunits + a, b - a, p.items, nullptr, nullptr, e, v, shrink, true, true, s);
   return grid_units<GR_PROJECT>(p, false, p.bunits + a, b - a, p.items, nullptr, grid, nullptr, e, v, shrink, s,
                                 false);
 }
 
 int grid_blocks_begin(const Plan& p, hipStream_t s) {
+  if (p.dde.on()) return dde_zero_patches(p, s);
   return zero_c64(p.halo, size_t(p.n_tiles) * ring_cells(p.tile), s);
 }
 
 int grid_blocks_end(const Plan& p, float2* grid, hipStream_t s) {
+  if (p.dde.on()) return dde_merge(p, grid, true, s);
   switch (p.tile) {
     case 16: launch_halo<16>(p, grid, false, s); break;
     case 32: launch_halo<32>(p, grid, false, s); break;

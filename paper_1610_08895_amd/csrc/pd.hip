@@ -35,6 +35,9 @@ struct ri_pd_s {
   float* xt = nullptr;
   float* s = nullptr;
   float* st = nullptr;     // s~ = Psi s
+  // weights of a weighted l1 prior (b*n*n, the layout of s; null: the plain prior), which
+  // make the bound of step 13's clip alpha w_k per coefficient (reweighted SARA)
+  float* wts = nullptr;
   float2* sum = nullptr;   // sum_i M_i^dagger v~_i on the K x K grid
   double* eps = nullptr;   // d
   double* stats = nullptr; // d x 2
@@ -114,6 +117,7 @@ void destroy_pd(ri_pd_s* P) {
   dev_free(P->xt);
   dev_free(P->s);
   dev_free(P->st);
+  dev_free(P->wts);
   dev_free(P->sum);
   dev_free(P->eps);
   dev_free(P->stats);
@@ -144,8 +148,29 @@ int refresh_sum(ri_pd_s* P, hipStream_t s) {
 
 int sparsity_branch(ri_pd_s* P, hipStream_t s) {
   // step 13 (Moreau form of the soft-threshold), then step 14
-  RI_STAGE(P, RI_STAGE_PSI_ADJ, s, psi_adj_apply(*P->sara, P->xt, P->s, true, P->alpha, s));
+  RI_STAGE(P, RI_STAGE_PSI_ADJ, s, psi_adj_apply(*P->sara, P->xt, P->s, true, P->alpha, s, P->wts));
   RI_STAGE(P, RI_STAGE_PSI_SYNTH, s, psi_apply(*P->sara, P->s, P->st, s));
+  return RI_OK;
+}
+
+// w_k = delta / (delta + |c_k|) in place, c = Psi^dagger x
+__global__ __launch_bounds__(256) void k_reweight(size_t count, float delta, float* __restrict__ w) {
+  for (size_t k = size_t(blockIdx.x) * 256 + threadIdx.x; k < count; k += size_t(gridDim.x) * 256)
+    w[k] = delta / (delta + fabsf(w[k]));
+}
+
+__global__ __launch_bounds__(256) void k_fill(size_t count, float v, float* __restrict__ w) {
+  for (size_t k = size_t(blockIdx.x) * 256 + threadIdx.x; k < count; k += size_t(gridDim.x) * 256) w[k] = v;
+}
+
+unsigned grid_for(size_t count) { return unsigned(std::min<size_t>((count + 255) / 256, 8192)); }
+
+int ensure_weights(ri_pd_s* P, hipStream_t s) {
+  if (P->wts) return RI_OK;
+  const size_t nb = size_t(P->sara->b) * P->plan->n * P->plan->n;
+  RI_TRY(dev_alloc(&P->wts, nb));
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(nb)), dim3(256), 0, s, nb, 1.f, P->wts);
+  RI_LAUNCH_CHECK();
   return RI_OK;
 }
 
@@ -371,6 +396,11 @@ int ri_pd_get(ri_pd P, int which, void* buf, size_t bytes, hipStream_t stream) {
     case RI_PD_S: src = P->s; need = size_t(P->sara->b) * N * 4; break;
     case RI_PD_V: src = P->v; need = size_t(P->plan->M) * 8; break;
     case RI_PD_E: src = P->e; need = size_t(P->plan->M) * 8; break;
+    case RI_PD_W:
+      if (!P->wts) return fail(RI_ESTATE, "the solver has no weights (plain l1 prior)");
+      src = P->wts;
+      need = size_t(P->sara->b) * N * 4;
+      break;
     case RI_PD_ITER:
       if (bytes != sizeof(int64_t)) return fail(RI_EINVAL, "ITER needs %zu bytes", sizeof(int64_t));
       *static_cast<int64_t*>(buf) = P->iter;
@@ -383,7 +413,13 @@ int ri_pd_get(ri_pd P, int which, void* buf, size_t bytes, hipStream_t stream) {
 }
 
 int ri_pd_set(ri_pd P, int which, const void* buf, size_t bytes, hipStream_t stream) {
-  if (!P || !buf) return fail(RI_EINVAL, "NULL argument");
+  if (!P) return fail(RI_EINVAL, "NULL argument");
+  if (which == RI_PD_W && !buf) {  // back to the plain l1 prior
+    if (bytes != 0) return fail(RI_EINVAL, "clearing the weights takes buf = NULL and bytes = 0");
+    ri::dev_free(P->wts);
+    return RI_OK;
+  }
+  if (!buf) return fail(RI_EINVAL, "NULL argument");
   const size_t N = size_t(P->plan->n) * P->plan->n;
   void* dst = nullptr;
   size_t need = 0;
@@ -392,6 +428,12 @@ int ri_pd_set(ri_pd P, int which, const void* buf, size_t bytes, hipStream_t str
     case RI_PD_XTILDE: dst = P->xt; need = N * 4; break;
     case RI_PD_S: dst = P->s; need = size_t(P->sara->b) * N * 4; break;
     case RI_PD_V: dst = P->v; need = size_t(P->plan->M) * 8; break;
+    case RI_PD_W:
+      need = size_t(P->sara->b) * N * 4;
+      if (bytes != need) return fail(RI_EINVAL, "state %d needs %zu bytes, got %zu", which, need, bytes);
+      RI_TRY(ri::ensure_weights(P, stream));
+      dst = P->wts;
+      break;
     case RI_PD_ITER:
       if (bytes != sizeof(int64_t)) return fail(RI_EINVAL, "ITER needs %zu bytes", sizeof(int64_t));
       P->iter = *static_cast<const int64_t*>(buf);
@@ -401,6 +443,24 @@ int ri_pd_set(ri_pd P, int which, const void* buf, size_t bytes, hipStream_t str
   if (bytes != need) return fail(RI_EINVAL, "state %d needs %zu bytes, got %zu", which, need, bytes);
   RI_HIP(hipMemcpyAsync(dst, buf, bytes, hipMemcpyDeviceToDevice, stream));
   if (which == RI_PD_V) return ri::refresh_sum(P, stream);
+  return RI_OK;
+}
+
+int ri_pd_reweight(ri_pd P, double delta, hipStream_t stream) {
+  if (!P) return fail(RI_EINVAL, "pd is NULL");
+  if (!(delta > 0) || !std::isfinite(delta)) return fail(RI_EINVAL, "delta = %g must be positive and finite", delta);
+  RI_TRY(ri::ensure_weights(P, stream));
+  const size_t nb = size_t(P->sara->b) * P->plan->n * P->plan->n;
+  // Psi^dagger x into the weights' storage, then w = delta / (delta + |.|) in place
+  RI_TRY(ri::psi_adj_apply(*P->sara, P->x, P->wts, false, 0.f, stream));
+  hipLaunchKernelGGL(ri::k_reweight, dim3(ri::grid_for(nb)), dim3(256), 0, stream, nb, float(delta), P->wts);
+  RI_LAUNCH_CHECK();
+  return RI_OK;
+}
+
+int ri_pd_weighted(ri_pd P, int* out) {
+  if (!P || !out) return fail(RI_EINVAL, "NULL argument");
+  *out = P->wts != nullptr;
   return RI_OK;
 }
 
@@ -436,7 +496,7 @@ int ri_pd_step_vjp(ri_pd P, const uint8_t* mask, const float* x_new, const float
   RI_TRY(ri::vjp_param_grads(N, P->vj_z, P->vj_st, P->vj_g, tau, sigma, vs, P->vj_part, DOT_PARTS, pgrad, stream));
   // step 13 (through s~ = Psi s'), then x~bar = Psi abar
   RI_TRY(ri::psi_adj_apply(S, P->vj_z, P->vj_w, false, 0.f, stream));
-  RI_TRY(ri::vjp_clip(NB, s_new, P->alpha, P->vj_w, float(-tau * sigma), sbar, stream));
+  RI_TRY(ri::vjp_clip(NB, s_new, P->alpha, P->wts, P->vj_w, float(-tau * sigma), sbar, stream));
   RI_TRY(ri::psi_apply(S, sbar, xtbar, stream));
   // steps 5-11 (through g = Re Phi^dagger v'), then x~bar += Re Phi_A^dagger rbar
   RI_TRY(ri::phi_apply(p, P->vj_z, reinterpret_cast<float*>(P->vj_phiz), nullptr, stream));

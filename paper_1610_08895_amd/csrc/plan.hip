@@ -75,6 +75,7 @@ void destroy_plan(Plan& p) {
   dev_free(p.empty_tiles);
   dev_free(p.norm_tmp);
   dev_free(p.dsum);
+  dde_destroy(p.dde);
 }
 
 // Reorders the visibilities of one work item (sorted by tile-local cell, key low word =
@@ -229,6 +230,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
     std::stable_sort(ts.begin(), ts.end(), [&](int a, int b) { return tile_vis[a] > tile_vis[b]; });
     for (int t : ts) units.push_back(make_int4(t, tile_cnt[t], tile_cnt[t + 1], tile_vis[t]));
   }
+  p.tile_units_host = units;
   // split dense tiles into slices of whole items
   std::vector<int> unit_patch;
   std::vector<std::vector<int>> tile_patches(p.n_tiles);

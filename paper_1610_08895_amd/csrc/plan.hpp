@@ -23,6 +23,26 @@ struct KBPoly {
 constexpr int FRAC_BITS = 20;
 constexpr unsigned FRAC_MASK = (1u << FRAC_BITS) - 1u;
 
+// The J = 8 weights phi(f + 3 - j) of a packed coordinate (f its fraction) and its cell
+// floor(kappa); tap j sits at cell floor(kappa) - 3 + j.
+__device__ __forceinline__ void kb_weights(unsigned packed, const KBPoly& P, float* w, int& cell) {
+  cell = int(packed >> FRAC_BITS);
+  const float f = float(packed & FRAC_MASK) * (1.0f / float(1u << FRAC_BITS));
+  const float x = 2.0f * f - 1.0f;
+  const float x2 = x * x;
+#pragma unroll
+  for (int j = 0; j < KB_J / 2; ++j) {
+    float e = P.e[j][KB_HALF_DEG], o = P.o[j][KB_HALF_DEG];
+#pragma unroll
+    for (int k = KB_HALF_DEG - 1; k >= 0; --k) {
+      e = fmaf(e, x2, P.e[j][k]);
+      o = fmaf(o, x2, P.o[j][k]);
+    }
+    w[j] = fmaf(x, o, e);
+    w[KB_J - 1 - j] = fmaf(-x, o, e);
+  }
+}
+
 // A work item: up to `bin` visibilities of one block that fall in one grid tile.
 // x = block, y = tile (ty * tiles_per_axis + tx), z = first plan position, w = count.
 // The device copies carry in y the item's index in block order instead (which indexes the
@@ -34,6 +54,21 @@ constexpr int PART_WAVES = 4;    // FP64 norm partials per work item (one per wa
 // Cells of a tile's halo ring: its (tile + 8)^2 region (the tile and the kernel's reach)
 // less the tile itself.
 constexpr int ring_cells(int tile) { return (tile + 8) * (tile + 8) - tile * tile; }
+
+// Direction-dependent effects folded into G (Eq. 1's D, Sec. II): each visibility's row of
+// G is its DDE kernel (jd x jd taps, jd = 2h + 1) convolved with the Kaiser-Bessel kernel,
+// S = J + 2h taps per axis, stored per visibility.
+struct Dde {
+  int h = -1;                     // -1: no DDEs (plain G)
+  int S = 0;                      // taps per axis
+  float2* w = nullptr;            // S * S * M weights, tap-major: w[t * M + m] (plan order)
+  float* wmax = nullptr;          // M: max over taps of |Re w| + |Im w| (fixed-point bound)
+  int4* tunits = nullptr;         // whole-tile units {tile, first, end, vis} over titems
+  int n_tunits = 0;
+  float2* patch = nullptr;        // n_tiles * (T + S - 1)^2: each tile's gridded region
+  uint8_t* tile_has = nullptr;    // n_tiles: tile has visibilities (its patch is written)
+  bool on() const { return h >= 0; }
+};
 
 struct Plan {
   int n = 0, K = 0, J = KB_J, d = 0;
@@ -88,6 +123,8 @@ struct Plan {
   float2* halo = nullptr;       // n_tiles * ring_cells(tile) halo rings of the gridding
   int n_empty = 0;
   int* empty_tiles = nullptr;   // n_empty tiles without visibilities
+  std::vector<int4> tile_units_host;  // whole-tile units over titems, densest first
+  Dde dde;
   int* active_count = nullptr;
   float* norm_tmp = nullptr;  // n * n scratch for power iterations
   double* dsum = nullptr;     // FP64 reduction scratch
@@ -118,8 +155,9 @@ int fft_adjoint_rows_update(const Plan& p, const PrimalUpdate& u, hipStream_t s)
 // stats[2i], stats[2i+1] = per-block sums of the degridding partials, active blocks only;
 // copied to out (may be null) with NaN rows for inactive blocks.  With eps and shrink
 // given, also shrink[i] = max(0, 1 - eps_i / ||r_i||) (0 inside the ball) for active blocks.
+// part: the per-item partials to reduce (null: the plan's).
 int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, hipStream_t s,
-                const double* eps = nullptr, float* shrink = nullptr);
+                const double* eps = nullptr, float* shrink = nullptr, const double* part = nullptr);
 // out[i] = ||y_i||^2 (FP64) for every block.
 int block_sumsq(const Plan& p, const float2* y, double* out, hipStream_t s);
 // y = G b for the items of active blocks (operator form).
@@ -132,6 +170,9 @@ int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid
 // All items (those of inactive blocks skipped), or the items of one block.
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
                     const uint8_t* mask, hipStream_t s);
+// The norms of degrid_residual over all items, without storing e, into the given partials
+// (2 * PART_WAVES * n_items doubles).
+int degrid_norms(const Plan& p, const float2* grid, const float2* y, const float2* v, double* part, hipStream_t s);
 int degrid_residual_block(const Plan& p, int block, const float2* grid, const float2* y, const float2* v,
                           float2* e, hipStream_t s);
 // PD projection pass: v_new = (v + e) shrink_i (shrink from block_stats); grid += G^dagger
@@ -154,6 +195,18 @@ int grid_project_block(const Plan& p, int block, const float2* e, float2* v, con
 int grid_blocks_end(const Plan& p, float2* grid, hipStream_t s);
 // grid = G^dagger v over all items (rebuilds the running sum from scratch).
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s);
+
+// ---- DDE-aware G (dde.hip); used by the functions above when p.dde.on() ----
+int dde_degrid(const Plan& p, const int4* units, int nunits, const Item* items, const uint8_t* mask,
+               const float2* grid, float2* out, const float2* y, const float2* v, double* part, hipStream_t s);
+// gridding over whole-tile units into the tiles' patches (ADD: added to them, per-block use)
+int dde_grid(const Plan& p, const int4* units, int nunits, const Item* items, const uint8_t* mask,
+             const float2* y, const float2* e, float2* v, const float* shrink, bool project, bool add_patch,
+             hipStream_t s);
+// grid (=, or += with add) the sum of the patches covering each cell
+int dde_merge(const Plan& p, float2* grid, bool add, hipStream_t s);
+int dde_zero_patches(const Plan& p, hipStream_t s);
+void dde_destroy(Dde& dd);
 
 // ---- reductions (reduce.hip) ----
 int zero_f32(float* p, size_t n, hipStream_t s);

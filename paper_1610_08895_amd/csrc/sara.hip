@@ -10,8 +10,9 @@
 // output pairs (2q, 2q + 1) from the same coefficients a[q - u], d[q - u].  Analysis of
 // level 1 reads x~ once per wavelet from L2; the dual update of step 13,
 // s = clip(s + Psi^dagger x~, -alpha, alpha), is applied as each coefficient is produced,
-// with the old coefficients loaded before the input is staged.  The last synthesis level
-// sums all bases in registers.
+// with the old coefficients loaded before the input is staged; for the weighted l1 prior of
+// reweighted SARA the bound is alpha w_k, with the weights w laid out like s.  The last
+// synthesis level sums all bases in registers.
 #include <cmath>
 #include <new>
 #include <vector>
@@ -54,10 +55,17 @@ struct DwtArgs {
   int n, m, level, levels, dirac, nw;
   int clip;
   float alpha;
+  const float* wts;  // per-coefficient weights of the clip bound (layout of s), or null
 };
 
-__device__ __forceinline__ void put_coef(float* p, float v, int clip, float alpha) {
-  *p = clip ? clampf(*p + v, alpha) : v;
+// bound of the clip at coefficient k of s: alpha, or alpha w_k (the same FP32 product
+// wherever it is formed, so a clipped value equals the bound exactly)
+__device__ __forceinline__ float clip_bound(const DwtArgs& A, size_t k) {
+  return A.wts != nullptr ? A.alpha * A.wts[k] : A.alpha;
+}
+
+__device__ __forceinline__ void put_coef(const DwtArgs& A, size_t k, float v) {
+  A.s[k] = A.clip ? clampf(A.s[k] + v, clip_bound(A, k)) : v;
 }
 
 // One analysis level for wavelet w with filters of (compile-time) length L on an output
@@ -77,12 +85,18 @@ __device__ __forceinline__ void analysis_tile(const DwtArgs& A, const float* __r
   const int pi = threadIdx.x / TO, pj = threadIdx.x - (threadIdx.x / TO) * TO;
   const int qi = i0 + pi, qj = j0 + pj;
   const bool mine = qi < mo && qj < mo;
-  float old[4] = {0.f, 0.f, 0.f, 0.f};
+  float old[4] = {0.f, 0.f, 0.f, 0.f}, bnd[4] = {A.alpha, A.alpha, A.alpha, A.alpha};
+  const size_t sbo = size_t(w + A.dirac) * n * n;
+  const size_t ko[4] = {size_t(qi) * n + qj, size_t(qi) * n + mo + qj, size_t(mo + qi) * n + qj,
+                        size_t(mo + qi) * n + mo + qj};
   if (A.clip && mine) {
-    if (A.level == A.levels) old[0] = sb[size_t(qi) * n + qj];
-    old[1] = sb[size_t(qi) * n + mo + qj];
-    old[2] = sb[size_t(mo + qi) * n + qj];
-    old[3] = sb[size_t(mo + qi) * n + mo + qj];
+    if (A.level == A.levels) old[0] = sb[ko[0]];
+    old[1] = sb[ko[1]];
+    old[2] = sb[ko[2]];
+    old[3] = sb[ko[3]];
+    if (A.wts != nullptr)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bnd[c] = clip_bound(A, sbo + ko[c]);
   }
   for (int idx = threadIdx.x; idx < RE * RE; idx += ST) {
     const int ly = idx / RE, lx = idx - ly * RE;
@@ -112,12 +126,12 @@ __device__ __forceinline__ void analysis_tile(const DwtArgs& A, const float* __r
     hl = fmaf(gw[t], l, hl);
     hh = fmaf(gw[t], h, hh);
   }
-  auto put = [&](float* p, float old_v, float v) { *p = A.clip ? clampf(old_v + v, A.alpha) : v; };
+  auto put = [&](int c, float v) { sb[ko[c]] = A.clip ? clampf(old[c] + v, bnd[c]) : v; };
   if (A.level < A.levels) A.tmp[w * A.tmp_stride + A.out_off + size_t(qi) * mo + qj] = ll;
-  else put(&sb[size_t(qi) * n + qj], old[0], ll);
-  put(&sb[size_t(qi) * n + mo + qj], old[1], lh);
-  put(&sb[size_t(mo + qi) * n + qj], old[2], hl);
-  put(&sb[size_t(mo + qi) * n + mo + qj], old[3], hh);
+  else put(0, ll);
+  put(1, lh);
+  put(2, hl);
+  put(3, hh);
 }
 
 #define RI_SWITCH_L(LEN, CALL)          \
@@ -145,7 +159,7 @@ __global__ __launch_bounds__(ST) void k_dwt_level(DwtArgs A, const float* __rest
   if (z == A.nw) {  // Dirac basis at level 1: coefficient = pixel
     for (int idx = threadIdx.x; idx < 4 * TO * TO; idx += ST) {
       const int r = 2 * i0 + idx / (2 * TO), c = 2 * j0 + idx % (2 * TO);
-      if (r < n && c < n) put_coef(&A.s[size_t(r) * n + c], A.x[size_t(r) * n + c], A.clip, A.alpha);
+      if (r < n && c < n) put_coef(A, size_t(r) * n + c, A.x[size_t(r) * n + c]);
     }
     return;
   }
@@ -331,11 +345,11 @@ __global__ __launch_bounds__(ST) void k_idwt_top(IdwtArgs A, const float* __rest
 
 unsigned tiles(int outputs, int t) { return unsigned((outputs + t - 1) / t); }
 
-int analysis(const Sara& S, const float* x, float* s, bool clip, float alpha, hipStream_t st) {
+int analysis(const Sara& S, const float* x, float* s, bool clip, float alpha, const float* wts, hipStream_t st) {
   for (int lev = 1; lev <= S.levels; ++lev) {
     const int m = S.n >> (lev - 1), mo = m / 2;
     DwtArgs A{x, S.tmp, S.tmp_stride, lev >= 2 ? S.tmp_off[lev - 1] : 0, lev < S.levels ? S.tmp_off[lev] : 0,
-              s, S.n, m, lev, S.levels, S.dirac, S.nw, clip ? 1 : 0, alpha};
+              s, S.n, m, lev, S.levels, S.dirac, S.nw, clip ? 1 : 0, alpha, wts};
     const int z = S.nw + ((lev == 1 && S.dirac) ? 1 : 0);
     if (z == 0) continue;
     hipLaunchKernelGGL(k_dwt_level, dim3(tiles(mo, TO), tiles(mo, TO), z), dim3(ST), 0, st, A, S.dfilt,
@@ -425,8 +439,9 @@ int create_sara(Sara& S, int n, int levels, uint32_t bases) {
 
 }  // namespace
 
-int psi_adj_apply(const Sara& S, const float* x, float* s, bool clip, float alpha, hipStream_t st) {
-  return analysis(S, x, s, clip, alpha, st);
+int psi_adj_apply(const Sara& S, const float* x, float* s, bool clip, float alpha, hipStream_t st,
+                  const float* wts) {
+  return analysis(S, x, s, clip, alpha, wts, st);
 }
 
 int psi_apply(const Sara& S, const float* s, float* x, hipStream_t st) {

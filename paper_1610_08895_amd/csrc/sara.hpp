@@ -34,8 +34,10 @@ struct Sara {
   double* dsum = nullptr;
 };
 
-// s = Psi^dagger x, or with clip: s = clip(s + Psi^dagger x, -alpha, alpha) (step 13 Moreau form).
-int psi_adj_apply(const Sara& S, const float* x, float* s, bool clip, float alpha, hipStream_t st);
+// s = Psi^dagger x, or with clip: s = clip(s + Psi^dagger x, -alpha, alpha) (step 13 Moreau form);
+// with weights wts (b*n*n, the layout of s) the bound of coefficient k is alpha * wts[k].
+int psi_adj_apply(const Sara& S, const float* x, float* s, bool clip, float alpha, hipStream_t st,
+                  const float* wts = nullptr);
 // x = Psi s.
 int psi_apply(const Sara& S, const float* s, float* x, hipStream_t st);
 

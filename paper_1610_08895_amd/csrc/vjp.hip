@@ -72,9 +72,12 @@ __global__ void k_dot2_final(const double* __restrict__ part, int nparts, double
 }
 
 __global__ __launch_bounds__(VT) void k_vjp_clip(size_t count, const float* __restrict__ s_new, float alpha,
-                                                 const float* __restrict__ w, float c, float* __restrict__ sbar) {
-  for (size_t k = size_t(blockIdx.x) * VT + threadIdx.x; k < count; k += size_t(gridDim.x) * VT)
-    sbar[k] = fabsf(s_new[k]) < alpha ? sbar[k] + c * w[k] : 0.f;
+                                                 const float* __restrict__ wts, const float* __restrict__ w, float c,
+                                                 float* __restrict__ sbar) {
+  for (size_t k = size_t(blockIdx.x) * VT + threadIdx.x; k < count; k += size_t(gridDim.x) * VT) {
+    const float bound = wts != nullptr ? alpha * wts[k] : alpha;  // the forward clip's bound
+    sbar[k] = fabsf(s_new[k]) < bound ? sbar[k] + c * w[k] : 0.f;
+  }
 }
 
 __global__ __launch_bounds__(VT) void k_axpy(int n, float a, const float* __restrict__ x, float* __restrict__ y) {
@@ -170,8 +173,9 @@ int vjp_param_grads(int n, const float* zbar, const float* st, const float* g, d
   return RI_OK;
 }
 
-int vjp_clip(size_t count, const float* s_new, float alpha, const float* w, float c, float* sbar, hipStream_t s) {
-  hipLaunchKernelGGL(k_vjp_clip, dim3(blocks_for(count)), dim3(VT), 0, s, count, s_new, alpha, w, c, sbar);
+int vjp_clip(size_t count, const float* s_new, float alpha, const float* wts, const float* w, float c, float* sbar,
+             hipStream_t s) {
+  hipLaunchKernelGGL(k_vjp_clip, dim3(blocks_for(count)), dim3(VT), 0, s, count, s_new, alpha, wts, w, c, sbar);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }

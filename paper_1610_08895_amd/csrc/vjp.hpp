@@ -13,8 +13,9 @@ int vjp_primal(int n, const float* x_new, float* xbar, const float* xtbar, float
 // part: 2 * nparts doubles of scratch)
 int vjp_param_grads(int n, const float* zbar, const float* st, const float* g, double tau, double sigma,
                     double varsigma, double* part, int nparts, double* pgrad, hipStream_t s);
-// sbar <- (sbar + c w) [|s_new| < alpha]
-int vjp_clip(size_t count, const float* s_new, float alpha, const float* w, float c, float* sbar, hipStream_t s);
+// sbar <- (sbar + c w) [|s_new| < bound], bound = alpha, or alpha * wts[k] with weights
+int vjp_clip(size_t count, const float* s_new, float alpha, const float* wts, const float* w, float c, float* sbar,
+             hipStream_t s);
 // y += a x
 int axpy(int n, float a, const float* x, float* y, hipStream_t s);
 // Per-block FP64 partials needed by vjp_ball: d * ball_chunks(p) doubles.

@@ -59,6 +59,19 @@ class Plan:
     def handle(self):
         return self._h
 
+    def set_dde(self, d):
+        """Direction-dependent effects in G (ri_plan_dde): d (M, jd, jd) complex DDE kernels in
+        user order, or None to remove them."""
+        if d is None:
+            L.check(L.load().ri_plan_dde(self._h, 0, None, _stream()))
+            self.jd = 0
+            return
+        d = np.ascontiguousarray(d, dtype=np.complex64)
+        if d.ndim != 3 or d.shape[0] != self.M or d.shape[1] != d.shape[2]:
+            raise ValueError("d must be (M, jd, jd)")
+        L.check(L.load().ri_plan_dde(self._h, int(d.shape[1]), d.ctypes.data, _stream()))
+        self.jd = int(d.shape[1])
+
     def order(self):
         out = np.empty(self.M, dtype=np.int64)
         L.check(L.load().ri_plan_order(self._h, out.ctypes.data))
@@ -232,10 +245,25 @@ class PD:
         L.check(L.load().ri_pd_stage_times(self._h, tot.ctypes.data, cnt.ctypes.data, n))
         return {name: (float(tot[i]), int(cnt[i])) for i, name in enumerate(L.STAGES)}
 
+    def reweight(self, delta):
+        """Weights w = delta / (delta + |Psi^dagger x|) of the weighted l1 prior, from the
+        current x (ri_pd_reweight); later steps clip at alpha w."""
+        L.check(L.load().ri_pd_reweight(self._h, float(delta), _stream()))
+
+    @property
+    def weighted(self):
+        v = ctypes.c_int()
+        L.check(L.load().ri_pd_weighted(self._h, ctypes.byref(v)))
+        return bool(v.value)
+
+    def unweight(self):
+        """Back to the plain l1 prior."""
+        L.check(L.load().ri_pd_set(self._h, L.RI_PD_W, None, 0, _stream()))
+
     def _shape(self, which):
         n = self.plan.n
         return {L.RI_PD_X: ((n, n), torch.float32), L.RI_PD_XTILDE: ((n, n), torch.float32),
-                L.RI_PD_S: ((self.sara.b, n, n), torch.float32),
+                L.RI_PD_S: ((self.sara.b, n, n), torch.float32), L.RI_PD_W: ((self.sara.b, n, n), torch.float32),
                 L.RI_PD_V: ((self.plan.M,), torch.complex64), L.RI_PD_E: ((self.plan.M,), torch.complex64)}[which]
 
     def get(self, which, out=None):

@@ -13,6 +13,7 @@ import math
 import numpy as np
 import torch
 
+from . import _lib as L
 from ._lib import SCHED_ADAPTIVE, SCHED_DRAW, SCHED_REFRESH, SCHED_UPDATE
 from .ops import PD, DeviceSchedule, Plan, Sara, probabilities, residual_energy
 
@@ -36,6 +37,23 @@ class Schedule:
     p_max: float = 0.5
     p_vec: tuple = ()
     refresh_every: int = 0
+
+
+@dataclasses.dataclass
+class Reweight:
+    """Reweighted SARA: every `every` iterations the weights of the weighted l1 prior become
+    w = delta / (delta + |Psi^dagger x|) at the current x, with delta = delta0, delta0 beta,
+    delta0 beta^2, ... (the first `every` iterations use w = 1, the plain prior)."""
+
+    every: int
+    delta0: float
+    beta: float = 0.5
+
+    def delta(self, t):
+        """delta of the reweighting before iteration t, or None if t is not one."""
+        if t <= 0 or t % self.every:
+            return None
+        return self.delta0 * self.beta ** (t // self.every - 1)
 
 
 def step_sizes(psi_norm, phi_norm, tau=0.49):
@@ -102,14 +120,19 @@ class Solver:
             self.pd.step(self.mask_dev, self.stats_dev)
 
     def prepare(self, iterations, schedule: Schedule = Schedule(), uniforms=None, masks=None, graph=False,
-                seed=0):
+                seed=0, reweight: Reweight = None):
         """A batched run of `iterations` steps, prepared but not started (see `run`): call
         its step() once per iteration, then history().  Nothing syncs with the host between
         steps."""
-        return BatchedRun(self, iterations, schedule, uniforms, masks, graph, seed)
+        return BatchedRun(self, iterations, schedule, uniforms, masks, graph, seed, reweight)
+
+    def _start_weights(self, reweight):
+        if reweight is not None and not self.pd.weighted:  # w = 1: the plain prior, same step
+            n, b = self.plan.n, self.sara.b
+            self.pd.set(L.RI_PD_W, torch.ones(b, n, n, dtype=torch.float32, device="cuda"))
 
     def run(self, iterations, schedule: Schedule = Schedule(), uniforms=None, masks=None, refresh=64,
-            x_true=None, snr_every=0, graph=False, plain=False, callback=None, seed=0):
+            x_true=None, snr_every=0, graph=False, plain=False, callback=None, seed=0, reweight: Reweight = None):
         """Run `iterations` steps.  Masks come from `masks` (replayed), else from
         `uniforms` (T x d) against the schedule's probabilities, else from uniforms drawn
         here with np.random.default_rng(seed) (only p = 1 without either runs every block
@@ -118,12 +141,14 @@ class Solver:
         (ri_sched_step), so iterations follow each other without a host round trip; the
         plain form (per-block launches, which need the mask on the host) selects them on
         the host.  `refresh` rebuilds the running sum of G_i^dagger v_i every that many
-        steps.  Returns a history dict (masks and probabilities per iteration, SNR)."""
+        steps.  `reweight` runs reweighted SARA (weights refreshed every `every` steps).
+        Returns a history dict (masks and probabilities per iteration, SNR)."""
         if plain:
             T = int(iterations)
             p_fixed, uniforms, masks, _ = _draws(self.plan.d, T, schedule, uniforms, masks, seed)
-            return self._run_host(T, schedule, p_fixed, uniforms, masks, refresh, x_true, snr_every, callback)
-        r = self.prepare(iterations, schedule, uniforms, masks, graph, seed)
+            return self._run_host(T, schedule, p_fixed, uniforms, masks, refresh, x_true, snr_every, callback,
+                                  reweight)
+        r = self.prepare(iterations, schedule, uniforms, masks, graph, seed, reweight)
         snrs = []
         for t in range(r.T):
             r.step()
@@ -137,13 +162,16 @@ class Solver:
         h["snr"] = snrs
         return h
 
-    def _run_host(self, T, schedule, p_fixed, uniforms, masks, refresh, x_true, snr_every, callback):
+    def _run_host(self, T, schedule, p_fixed, uniforms, masks, refresh, x_true, snr_every, callback, reweight):
         """The plain form's loop: blocks drawn on the host, one step at a time."""
         d = self.plan.d
         adaptive = p_fixed is None
         c = self.initial_energy() if adaptive else None
         hist = {"masks": [], "p": [], "snr": []}
+        self._start_weights(reweight)
         for t in range(T):
+            if reweight is not None and reweight.delta(t) is not None:
+                self.pd.reweight(reweight.delta(t))
             if adaptive and schedule.refresh_every and t > 0 and t % schedule.refresh_every == 0:
                 c = self.energy()
             p = probabilities(c, schedule.n_nodes, schedule.p_min, schedule.p_max)[0] if adaptive else p_fixed
@@ -208,8 +236,10 @@ class BatchedRun:
     K-th iteration is preceded by Eq. 13 at x for all blocks (ri_pd_residual).  With
     graph=True the two sequences are captured once each and replayed."""
 
-    def __init__(self, solver, iterations, schedule, uniforms, masks, graph, seed):
+    def __init__(self, solver, iterations, schedule, uniforms, masks, graph, seed, reweight=None):
         self.sol, self.T, self.graph = solver, int(iterations), graph
+        self.reweight = reweight
+        solver._start_weights(reweight)
         d = solver.plan.d
         p_fixed, uniforms, masks, every_block = _draws(d, self.T, schedule, uniforms, masks, seed)
         adaptive = p_fixed is None
@@ -238,6 +268,8 @@ class BatchedRun:
         self.sol.pd.step(self.mask, self.sol.stats_dev)
 
     def step(self):
+        if self.reweight is not None and self.reweight.delta(self.t) is not None:
+            self.sol.pd.reweight(self.reweight.delta(self.t))  # between two steps, outside the graphs
         exact = bool(self.K) and self.t > 0 and self.t % self.K == 0
         fn = self._body_refresh if exact else self._body
         if self.graph:

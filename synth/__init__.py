@@ -226,3 +226,21 @@ def add_noise(w: Workload, y0: np.ndarray, block_off: np.ndarray):
     s = noise_sigma(y0, w.isnr_db)
     y = np.asarray(y0, dtype=np.complex128) + complex_noise(y0.size, s, np.random.default_rng(w.seed(SEED_NOISE)))
     return y, s, l2_ball_radii(block_off, s)
+
+
+def dde_taps(M: int, jd: int, rng: np.random.Generator, strength: float = 0.2) -> np.ndarray:
+    """Per-visibility direction-dependent-effect kernels, (M, jd, jd) complex128.
+
+    Entry [m, h + q, h + p] (h = jd // 2, -h <= p, q <= h) is the coefficient d_m[q, p] of a
+    smooth, band-limited DDE D_m(l) = sum d_m[q, p] exp(-2 pi i (p l_x + q l_y) / K) on the
+    oversampled grid of K cells per axis: a unit central term plus complex Gaussian terms of
+    standard deviation `strength` exp(-(p^2 + q^2) / 2), independent per visibility.
+    Synthetic stand-in for calibrated DDE kernels (antenna beams, ionosphere)."""
+    if jd < 1 or jd % 2 == 0:
+        raise ValueError("jd must be odd and positive")
+    h = jd // 2
+    q, p = np.meshgrid(np.arange(-h, h + 1), np.arange(-h, h + 1), indexing="ij")
+    env = strength * np.exp(-(p ** 2 + q ** 2) / 2.0)
+    d = (rng.standard_normal((M, jd, jd)) + 1j * rng.standard_normal((M, jd, jd))) * (env / np.sqrt(2.0))
+    d[:, h, h] += 1.0
+    return d

@@ -110,8 +110,8 @@ def test_unrolled_gradient_matches_oracle(R, checkpoint):
     s_gpu, g = _gpu_grad(R, plan, yp, eps, prm, masks, x, checkpoint)
     print(f"SNR {s_gpu:.6f} / {s_ref:.6f}; dtau {g[0]:.7g} / {dtau:.7g}; dsigma {g[1]:.7g} / {dsig:.7g}")
     assert s_gpu == pytest.approx(s_ref, abs=1e-3)
-    assert g[0] == pytest.approx(dtau, rel=2e-3)
-    assert g[1] == pytest.approx(dsig, rel=2e-3)
+    assert g[0] == pytest.approx(dtau, rel=1e-4)
+    assert g[1] == pytest.approx(dsig, rel=1e-4)
 
 
 def test_unrolled_gradient_reference_512(R):
@@ -135,5 +135,5 @@ def test_unrolled_gradient_reference_512(R):
     print(f"SNR {s_gpu:.6f} / {ref['snr']:.6f}; dtau {g[0]:.7g} / {ref['dsnr_dtau']:.7g}; "
           f"dsigma {g[1]:.7g} / {ref['dsnr_dsigma']:.7g}")
     assert s_gpu == pytest.approx(ref["snr"], abs=1e-3)
-    assert g[0] == pytest.approx(ref["dsnr_dtau"], rel=2e-3)
-    assert g[1] == pytest.approx(ref["dsnr_dsigma"], rel=2e-3)
+    assert g[0] == pytest.approx(ref["dsnr_dtau"], rel=1e-4)
+    assert g[1] == pytest.approx(ref["dsnr_dsigma"], rel=1e-4)

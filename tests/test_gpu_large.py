@@ -51,6 +51,25 @@ def test_phi_sampled_parity_2048(R, big):
     assert rel_l2(y_user[pick], y_ref) < 1e-5
 
 
+def test_phi_adj_whole_blocks_2048(R, big):
+    """Phi^dagger at 2048^2 against the oracle with y nonzero on three whole blocks only: the
+    innermost, a middle one, and the outermost, which holds most of the uniform outliers
+    (relative l2 <= 1e-5)."""
+    w, inp, plan = big
+    off = inp.block_off
+    blocks = [0, plan.d // 2, plan.d - 1]
+    rng = np.random.default_rng(34)
+    y = np.zeros(w.M, np.complex128)
+    for i in blocks:
+        y[off[i]:off[i + 1]] = rng.standard_normal(off[i + 1] - off[i]) + 1j * rng.standard_normal(off[i + 1] - off[i])
+    r = np.hypot(inp.uv[off[-2]:off[-1], 0], inp.uv[off[-2]:off[-1], 1])
+    assert np.mean(r > 3 * np.pi / 4) > 0.5, "the last block is outlier-heavy"
+    meas = Measurement(inp.uv, off, (w.n, w.n))
+    ref = meas.phi_adj_real(y, blocks=blocks)
+    got = plan.phi_adj(torch.tensor(to_plan(y, plan.order()), dtype=torch.complex64, device="cuda")).cpu().numpy()
+    assert rel_l2(got, ref) < 1e-5
+
+
 def test_adjoint_identity_2048(R, big):
     w, inp, plan = big
     g = torch.Generator(device="cuda").manual_seed(32)

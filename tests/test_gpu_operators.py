@@ -228,3 +228,42 @@ def test_autotune_picks_a_candidate_and_caches(R, tmp_path):
     assert best in [dict(c) for c in cands] and len(times) == 2 and all(t > 0 for t in times.values())
     again, t2 = autotune.tune(n, uv, off, y, eps, candidates=cands, steps=3, cache=cache)
     assert again == best and t2 == {}
+
+
+def test_grid_point_carry_and_band_edge_coordinates(R):
+    """u-v on grid points (kappa = u K / 2 pi integral: u = 0, and the FP32 values nearest
+    2 pi k / K, whose kappa lands a hair above or below k), one unit in the last place either
+    side of them, fractions that round up to a whole cell in the plan's 20-bit fixed point
+    (the carry into the next cell), and the band edges u = -pi (FP32) and the largest FP32
+    below pi; mixed with random coordinates over several tiles and ragged blocks."""
+    n = 64
+    K = 2 * n
+    rng = np.random.default_rng(41)
+    ks = np.concatenate([np.arange(-6, 7), rng.integers(-K // 2, K // 2, 40), [-K // 2, K // 2 - 1]])
+    base = (2 * np.pi * ks / K).astype(np.float32)
+    vals = np.concatenate([base, np.nextafter(base, np.float32(np.inf)), np.nextafter(base, np.float32(-np.inf)),
+                           np.array([0.0, -np.pi, np.nextafter(np.float32(np.pi), np.float32(0))], np.float32)])
+    vals = vals[(vals >= np.float32(-np.pi)) & (vals < np.float32(np.pi))]
+    grid_uv = np.stack(np.meshgrid(vals, vals[::7]), -1).reshape(-1, 2).astype(np.float32)
+    kap = grid_uv.astype(np.float64) * K / (2 * np.pi)
+    frac = kap - np.floor(kap)
+    assert np.any(frac == 0.0), "some coordinates exactly on grid points"
+    assert np.any(frac >= 1.0 - 2.0 ** -21), "some fractions carry into the next cell"
+    rand_uv = synth.uv_coverage(6000, rng).astype(np.float32)
+    uv = np.concatenate([grid_uv, rand_uv])
+    rng.shuffle(uv)
+    M = uv.shape[0]
+    off = np.array([0, 5, 1300, 4000, M])  # ragged blocks
+    x = synth.sky(n, 5, 10, rng)
+    plan = R.Plan(n, uv, off)
+    order = plan.order()
+    meas = Measurement(uv, off, (n, n))
+    y = to_user(plan.phi(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy(), order)
+    assert rel_l2(y, meas.phi(x)) < TOL
+    w = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    xa = plan.phi_adj(torch.tensor(to_plan(w, order), dtype=torch.complex64, device="cuda")).cpu().numpy()
+    assert rel_l2(xa, meas.phi_adj_real(w)) < TOL
+    # the visibilities on the edge points alone, against the oracle one by one
+    sel = np.flatnonzero((uv[:, 0] == np.float32(-np.pi)) | (uv[:, 1] == np.float32(-np.pi)))
+    assert sel.size > 0
+    assert rel_l2(y[sel], meas.phi(x)[sel]) < TOL
