@@ -216,6 +216,16 @@ int ri_pd_refresh(ri_pd pd, hipStream_t stream);
  * Errors: RI_EINVAL (NULL pd or out), RI_ENOMEM, RI_EHIP. */
 int ri_pd_residual(ri_pd pd, double* out, hipStream_t stream);
 
+/* For callers that cannot allocate (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation): ri_pd_residual without any allocation.  The same
+ * out[2i] and out[2i+1], with the per-item partial norms and per-block sums kept in a
+ * static device array of 4 MiB (2^19 doubles) per GPU instead of library-allocated
+ * memory, and the residual itself not stored.  Needs 8 * n_items + 2 d doubles of it
+ * (n_items from ri_plan_info); larger plans are rejected with RI_EINVAL.  The array is
+ * shared by every call on one GPU: calls that overlap on one GPU race.  The plan's FFT grid
+ * is overwritten, as by ri_pd_residual.  Enqueue-only; errors: RI_EINVAL, RI_EHIP. */
+int ri_pd_residual_noalloc(ri_pd pd, double* out, hipStream_t stream);
+
 /* Stages of one iteration, for per-stage timing (each stage is one kernel launch in the
  * batched step; the plain step times all per-block launches of a stage together). */
 enum {

@@ -78,6 +78,7 @@ SIGNATURES = {
     "ri_sched_step": (c_int, [P(Sched), c_int, c_void_p]),
     "ri_pd_reweight": (c_int, [c_void_p, c_double, c_void_p]),
     "ri_plan_dde": (c_int, [c_void_p, c_int, c_void_p, c_void_p]),
+    "ri_pd_residual_noalloc": (c_int, [c_void_p, c_void_p, c_void_p]),
     "ri_pd_weighted": (c_int, [c_void_p, P(c_int)]),
 }
 

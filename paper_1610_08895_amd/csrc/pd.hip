@@ -16,6 +16,7 @@
 // V) rebuilds it from the stored v, bounding accumulated rounding.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -383,6 +384,66 @@ int ri_pd_residual(ri_pd P, double* out, hipStream_t stream) {
   RI_TRY(ri::fft_forward(p, P->x, p.grid, stream));
   RI_TRY(ri::degrid_residual(p, p.grid, P->y, P->v, P->res_e, nullptr, stream));
   return ri::block_stats(p, nullptr, P->stats, out, stream);
+}
+
+}  // extern "C"
+
+// ---- Eq. 13 at x without allocating, for callers that cannot allocate ----
+//
+// The per-item partial norms of the residual pass and the per-block statistics live in
+// this file-scope device array instead of memory the library allocates.  Every GPU the
+// library runs on holds its own copy until the process ends; its address is taken once per
+// device (with that device current) and only that address is passed to kernels.  Calls on
+// one GPU share the array: calls that overlap on different streams of one GPU race.
+// Nothing in it needs to start at zero (every partial the reduction reads is written first).
+namespace ri {
+namespace {
+constexpr size_t RESID_SCRATCH_DOUBLES = size_t(1) << 19;  // 4 MiB
+constexpr int MAX_DEVICES = 64;
+}  // namespace
+}  // namespace ri
+
+static __device__ __align__(256) double scratch[ri::RESID_SCRATCH_DOUBLES];
+
+namespace ri {
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_for_device(double** out) {
+  int dev = 0;
+  RI_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(RI_EINVAL, "device %d beyond the %d supported", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(RI_EHIP, "hipGetSymbolAddress of the residual scratch failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return RI_OK;
+}
+}  // namespace
+}  // namespace ri
+
+extern "C" {
+
+int ri_pd_residual_noalloc(ri_pd P, double* out, hipStream_t stream) {
+  if (!P || !out) return fail(RI_EINVAL, "pd and out must not be NULL");
+  const ri::Plan& p = *P->plan;
+  const size_t nparts = 2 * size_t(ri::PART_WAVES) * p.n_items, need = nparts + 2 * size_t(p.d);
+  if (need > ri::RESID_SCRATCH_DOUBLES)
+    return fail(RI_EINVAL, "the plan needs %zu doubles of scratch (%d work items, %d blocks); the static scratch "
+                "holds %zu", need, p.n_items, p.d, ri::RESID_SCRATCH_DOUBLES);
+  double* sc = nullptr;
+  RI_TRY(ri::scratch_for_device(&sc));
+  double* part = sc;
+  double* stats = sc + nparts;
+  RI_TRY(ri::fft_forward(p, P->x, p.grid, stream));
+  RI_TRY(ri::degrid_norms(p, p.grid, P->y, P->v, part, stream));
+  return ri::block_stats(p, nullptr, stats, out, stream, nullptr, nullptr, part);
 }
 
 int ri_pd_get(ri_pd P, int which, void* buf, size_t bytes, hipStream_t stream) {
