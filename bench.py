@@ -87,6 +87,12 @@ def phi_bytes(n, M):
     return 100 * n * n + 16 * M
 
 
+def dde_phi_bytes(n, M, S):
+    """Phi (or Phi^dagger) with DDE-aware G: the FFT part as for Phi (100N with the grid read
+    once) plus S^2 complex FP32 weights, coordinates and y per visibility."""
+    return 100 * n * n + (8 * S * S + 16) * M
+
+
 def profile_record(kernel_stage, workload):
     """A committed counter record for a kernel, if it still matches the kernel's source."""
     path = os.path.join(ROOT, "profiles", f"{kernel_stage}_{workload}_traffic.json")
@@ -177,6 +183,8 @@ def main():
     ap.add_argument("--op-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="eager steps only (for counter runs)")
+    ap.add_argument("--workload", default=WORKLOAD, choices=["n1024_m4m_d64", "n2048_m16m_d128"],
+                    help="workload of the headline section (profiling runs of the large case)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the adaptive and 2048^2 operating points (for short profiling runs)")
     ap.add_argument("--tile", type=int, default=0, help="grid tile side (0: the autotuner's pick)")
@@ -204,7 +212,9 @@ def main():
     _lib.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    w = synth.WORKLOADS[WORKLOAD]
+    w = synth.WORKLOADS[args.workload]
+    if args.workload != WORKLOAD:
+        args.no_extra = True  # the extra operating points belong to the default workload's run
     t0 = time.time()
 
     # ---- tuning: the autotuner's pick for this workload (cached per device and size) ----
@@ -322,6 +332,31 @@ def main():
         log(f"reweighted: {ms_r:.4f} ms/iter")
         del sol_r
 
+    # ---- DDE-aware G: jd = 5 DDE kernels per visibility, S = 12 taps per axis ----
+    if not args.no_extra:
+        jd = 5
+        S = 8 + 2 * (jd // 2)
+        taps = synth.dde_taps(w.M, jd, np.random.default_rng(w.seed(6)))
+        t_d = time.time()
+        plan.set_dde(taps.astype(np.complex64))
+        del taps
+        dde_setup = time.time() - t_d
+        phid_ms, phida_ms = time_ops(plan, P["x_true"], y_plan, max(5, args.op_reps // 2))
+        sol_d = Solver(plan, sara, y_plan, eps, psi_norm, phi_norm)
+        ms_d, _, _ = time_run(sol_d, Schedule(), 5, 20)
+        del sol_d
+        plan.set_dde(None)
+        db = dde_phi_bytes(w.n, w.M, S)
+        extra["dde"] = {
+            "jd": jd, "taps_per_vis": S * S, "weight_bytes_per_vis": 8 * S * S, "setup_s": round(dde_setup, 2),
+            "phi_gvis_s": round(w.M / phid_ms / 1e6, 2), "phi_adj_gvis_s": round(w.M / phida_ms / 1e6, 2),
+            "phi_ms": round(phid_ms, 4), "phi_adj_ms": round(phida_ms, 4), "phi_algorithmic_bytes": db,
+            "phi_frac": round(db / (phid_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "phi_adj_frac": round(db / (phida_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "pd_iters_s": round(1e3 / ms_d, 2)}
+        log(f"DDE jd={jd}: Phi {phid_ms:.4f} ms, Phi^dagger {phida_ms:.4f} ms, PD {ms_d:.4f} ms/iter "
+            f"(setup {dde_setup:.1f}s)")
+
     # ---- CPU oracle baseline: one iteration of Algorithm 1 on the same workload ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -343,7 +378,7 @@ def main():
         opd.iteration(meas, osara, yb_o, eps, prm, st, mask)
         t_cpu = time.perf_counter() - t_a
         cpu = {"value": 1.0 / t_cpu, "unit": "iters/s", "cores": cores, "kind": "oracle",
-               "sample": f"1 iteration of Algorithm 1 on the full {WORKLOAD} workload, all 64 blocks active, "
+               "sample": f"1 iteration of Algorithm 1 on the full {w.name} workload, all {w.d} blocks active, "
                          f"FP64 numpy, the par-for over blocks and the per-basis wavelet loop on a pool of "
                          f"{cores} threads, {t_cpu:.1f} s"}
         log(f"cpu oracle: {t_cpu:.2f} s / iteration on {cores} threads")
@@ -372,7 +407,7 @@ def main():
         log(f"n2048: adaptive32 {ms5:.4f} ms/iter ({nb5:.1f} blocks, {nv5 / 1e6:.2f} M vis), p=1 {ms5_p1:.4f} ms, "
             f"Phi {phi5:.4f} ms, Phi^dagger {phia5:.4f} ms")
 
-    rec = profile_record(dom, WORKLOAD)
+    rec = profile_record(dom, w.name)
     out = {
         "metric": METRIC,
         "value": round(iters_s, 3),
@@ -386,7 +421,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "n": w.n, "M": w.M, "d": w.d, "p": 1.0, "tile": tile_used,
+        "config": {"workload": w.name, "n": w.n, "M": w.M, "d": w.d, "p": 1.0, "tile": tile_used,
                    "bin": tune.get("bin") or 1024, "slice_vis": tune.get("slice_vis") or -1,
                    "autotuned": tune_src != "command line", "tuning_source": tune_src,
                    "form": "batched persistent kernels" + ("" if args.no_graph else " + HIP graph") +

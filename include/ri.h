@@ -190,7 +190,10 @@ void ri_pd_destroy(ri_pd pd);
  * NULL = all), all active blocks of uneven size in one persistent launch per operator.
  * stats: device d x 2 float64 output; for active block i, stats[2i] = ||v_i + G_i b_i - y_i||^2
  * (the projection's residual) and stats[2i+1] = ||G_i b_i - y_i||^2 = ||Phi_i x~ - y_i||^2
- * (drives Eq. 13); inactive rows are set to NaN.  May be NULL.
+ * (drives Eq. 13); inactive rows are set to NaN.  May be NULL.  With mask NULL every block is
+ * active and sum_i M_i^dagger v~_i is rebuilt from the new v_i (the gridding then reads r
+ * and writes v, 24 bytes per visibility); with a mask the active blocks' changes are added
+ * to the kept sum.
  * Graph capture: the call only enqueues kernels (no allocation, no host sync, no memset);
  * the mask and stats pointers are baked into a captured graph.
  */
@@ -260,7 +263,8 @@ enum {
   RI_PD_S = 2,     /* b*n*n float32                                 */
   RI_PD_V = 3,     /* M complex float32, plan order                 */
   RI_PD_ITER = 4,  /* int64 iteration counter (host buffer)         */
-  RI_PD_E = 5,     /* M complex float32: G_i b_i - y_i of the last step's active blocks
+  RI_PD_E = 5,     /* M complex float32: r = v_i + G_i b_i - y_i (the argument of step 8's
+                      projection, v_i before the step) of the last step's active blocks
                       (read only)                                   */
   RI_PD_W = 6      /* b*n*n float32 weights w_k of the weighted l1 prior (layout of S);
                       set allocates them on first use, set with buf = NULL and bytes = 0
@@ -294,9 +298,8 @@ int ri_pd_weighted(ri_pd pd, int* out);
 
 /* Reverse (vector-Jacobian) sweep of one ri_pd_step with the pd's tau, sigma, varsigma
  * and alpha = kappa ||Psi||.  All pointers device.  From the forward step: mask (d, as
- * given to it), x_new (n*n, x after it), s_new (b*n*n, s after it), v_new and v_old
- * (M complex, v after and before it), e (M complex, RI_PD_E after it), stats (d x 2
- * FP64, as it returned them).  Adjoints, updated in place: on entry xbar, xtbar, sbar,
+ * given to it), x_new (n*n, x after it), s_new (b*n*n, s after it), v_new (M complex, v
+ * after it), r (M complex, RI_PD_E after it), stats (d x 2 FP64, as it returned them).  Adjoints, updated in place: on entry xbar, xtbar, sbar,
  * vbar (n*n, n*n, b*n*n, M complex) hold dL/d(x, x~, s, v) after the step, on return
  * dL/d(x, x~, s, v) before it; pgrad[0], pgrad[1] (FP64) are incremented by the step's
  * own contributions to dL/dtau and dL/dsigma.  Vector-Jacobian products used: clip ->
@@ -305,8 +308,8 @@ int ri_pd_weighted(ri_pd pd, int* out);
  * call allocates the sweep's scratch (about 10 n*n floats and M complex values).
  * Errors: RI_EINVAL (NULL pointer), RI_ENOMEM, RI_EHIP. */
 int ri_pd_step_vjp(ri_pd pd, const uint8_t* mask, const float* x_new, const float* s_new, const float* v_new,
-                   const float* v_old, const float* e, const double* stats, float* xbar, float* xtbar,
-                   float* sbar, float* vbar, double* pgrad, hipStream_t stream);
+                   const float* r, const double* stats, float* xbar, float* xtbar, float* sbar, float* vbar,
+                   double* pgrad, hipStream_t stream);
 
 /* ------------------------------------------------------------------------------------
  * Adaptive probabilities (Sec. IV)

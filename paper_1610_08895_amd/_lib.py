@@ -72,7 +72,7 @@ SIGNATURES = {
     "ri_pd_get": (c_int, [c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
     "ri_pd_set": (c_int, [c_void_p, c_int, c_void_p, c_size_t, c_void_p]),
     "ri_pd_step_vjp": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+                               c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ri_residual_energy": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
     "ri_probs": (c_int, [c_void_p, c_int, c_double, c_double, c_double, c_void_p, P(c_double)]),
     "ri_sched_step": (c_int, [P(Sched), c_int, c_void_p]),

@@ -114,10 +114,9 @@ class _UnrolledPD(torch.autograd.Function):
                 pd.set(w, v)
             tape = []
             for t in range(t0, min(t0 + C, T)):
-                v_old = pd.get(L.RI_PD_V).clone()
                 pd.step(masks[t], stats)
                 tape.append((masks[t], pd.get(L.RI_PD_X).clone(), pd.get(L.RI_PD_S).clone(),
-                             pd.get(L.RI_PD_V).clone(), v_old, pd.get(L.RI_PD_E).clone(), stats.clone()))
+                             pd.get(L.RI_PD_V).clone(), pd.get(L.RI_PD_E).clone(), stats.clone()))
             for rec in reversed(tape):
                 pd.step_vjp(*rec, xbar, xtbar, sbar, vbar, pgrad)
         grad = pgrad.to(device=ctx.params_device, dtype=ctx.params_dtype)

@@ -27,7 +27,11 @@ DEFAULT_CANDIDATES = (
 
 
 def _key(n, M, d):
-    return f"{torch.cuda.get_device_name(0)}|n={n}|M={M}|d={d}"
+    """Cache key: the device's architecture and compute-unit count (marketing names differ
+    between driver installs of the same part) and the problem size."""
+    props = torch.cuda.get_device_properties(0)
+    arch = getattr(props, "gcnArchName", "").split(":")[0] or torch.cuda.get_device_name(0)
+    return f"{arch}x{props.multi_processor_count}|n={n}|M={M}|d={d}"
 
 
 def cached(cache, n, M, d):
@@ -45,13 +49,12 @@ def time_candidate(n, uv, block_off, y_user, eps, tune, steps=10, warmup=3):
     sara = Sara(n)
     phin = 4.0 * n  # step sizes do not change the work of a step
     pd = PD(plan, sara, yp, eps, 0.49, 1.0 / 9.0, 1.0 / phin ** 2, 1e-3, 3.0, phin)
-    mask = torch.ones(plan.d, dtype=torch.uint8, device="cuda")
     for _ in range(warmup):
-        pd.step(mask)
+        pd.step()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(steps):
-        pd.step(mask)
+        pd.step()
     b.record()
     b.synchronize()
     ms = a.elapsed_time(b) / steps

@@ -93,7 +93,7 @@ __global__ __launch_bounds__(DT) void k_dde_weights(int64_t M, const uint2* __re
 enum { DD_APPLY = 0, DD_RESIDUAL = 1 };
 
 // Degridding over units {tile, first, end} of items; MODE as k_degrid in gridding.hip
-// (residual: e = G b - y into out and FP64 partial norms of r = v + e and e per wavefront).
+// (residual: r = v + G b - y into out and FP64 partial norms of r and of G b - y per wavefront).
 template <int T, int H, int MODE>
 __global__ __launch_bounds__(DT) void k_degrid_dde(const int4* __restrict__ units, int nunits,
                                                    const Item* __restrict__ items, const uint8_t* __restrict__ mask,
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(DT) void k_degrid_dde(const int4* __restrict__ unit
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int4 un = units[u];
-    bool any = mask == nullptr;
+    bool any = mask == nullptr && un.y < un.z;  // empty units fill gaps of the XCD order
     for (int q = un.y; q < un.z && !any; ++q) any = mask[items[q].x] != 0;
     if (!any) continue;
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(DT) void k_degrid_dde(const int4* __restrict__ unit
           const float2 yy = y[m], vv = v[m];
           const float2 e = make_float2(acc.x - yy.x, acc.y - yy.y);
           const float2 r = make_float2(vv.x + e.x, vv.y + e.y);
-          if (out != nullptr) out[m] = e;
+          if (out != nullptr) out[m] = r;
           sr += double(r.x) * r.x + double(r.y) * r.y;
           se += double(e.x) * e.x + double(e.y) * e.y;
         }
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(DT) void k_degrid_dde(const int4* __restrict__ unit
 }
 
 // Gridding with conjugate DDE weights over whole-tile units.  PROJECT: the values are the
-// step-8 dual changes (v_new = (v + e) shrink_i stored, v_new - v_old gridded), else y.
+// step-8 dual changes (v_new = r shrink_i stored, v_new - v_old gridded), else y.
 // The tile's region goes to its patch (stored, or added with ADDP).
 template <int T, int H, bool PROJECT, bool ADDP>
 __global__ __launch_bounds__(DT) void k_grid_dde(const int4* __restrict__ units, int nunits,
@@ -206,8 +206,8 @@ __global__ __launch_bounds__(DT) void k_grid_dde(const int4* __restrict__ units,
           const int64_t m = it.z + s;
           if (PROJECT) {
             const float sh = shrink[it.x];
-            const float2 vo = v[m], ee = e[m];
-            const float2 vn = make_float2((vo.x + ee.x) * sh, (vo.y + ee.y) * sh);
+            const float2 vo = v[m], rr = e[m];  // r = v_old + G b - y from the degridding
+            const float2 vn = make_float2(rr.x * sh, rr.y * sh);
             v[m] = vn;
             val[k] = make_float2(vn.x - vo.x, vn.y - vo.y);
           } else {

@@ -1,14 +1,17 @@
 // Interpolation G_i (degridding) and its adjoint G_i^dagger (gridding) over sorted
 // visibilities, with the per-block work of Algorithm 1 fused in:
 //
-//   degrid_residual  steps 5 and 8 (first half): e = G_i b_i - y_i, r = v_i + e, and the
-//                    FP64 block sums ||r_i||^2 (for the projection, Eq. 10) and ||e||^2
-//                    (for Eq. 13).
+//   degrid_residual  steps 5 and 8 (first half): r = v_i + G_i b_i - y_i stored, and the
+//                    FP64 block sums ||r_i||^2 (for the projection, Eq. 10) and
+//                    ||G_i b_i - y_i||^2 (for Eq. 13).
 //   grid_project     steps 8 (second half), 9 and 11: v_i <- r max(0, 1 - eps_i / ||r_i||)
 //                    (the Moreau form of v + Gb - P_B(v + Gb)), and the change
 //                    G_i^dagger (v_new - v_old) added into the running grid sum
 //                    sum_i M_i^dagger v~_i.  Blocks outside A are not visited, so their v_i
 //                    and v~_i stay as they are.
+//   grid_project_all with every block active: v_i <- r max(0, 1 - eps_i / ||r_i||) and the
+//                    sum rebuilt from scratch, G^dagger v_new stored (it reads r and writes
+//                    v, 24 bytes per visibility, and stores the grid instead of updating it).
 //
 // Visibilities are sorted by (block, tile, cell); a work item holds up to `bin`
 // visibilities of one block in one T x T grid tile.
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
     const int4 un = units[u];
-    bool any = mask == nullptr;
+    bool any = mask == nullptr && un.y < un.z;  // an empty unit fills a gap of the XCD order
     for (int q = un.y; q < un.z && !any; ++q) any = mask[items[q].x] != 0;
     if (!any) continue;
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
@@ -146,7 +149,7 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
           } else {
             const float2 e = make_float2(acc.x - yy[k].x, acc.y - yy[k].y);
             const float2 r = make_float2(vv[k].x + e.x, vv[k].y + e.y);
-            if (MODE == DG_RESIDUAL) out[it.z + s] = e;
+            if (MODE == DG_RESIDUAL) out[it.z + s] = r;
             sr += double(r.x) * r.x + double(r.y) * r.y;
             se += double(e.x) * e.x + double(e.y) * e.y;
           }
@@ -221,7 +224,9 @@ __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ 
   }
 }
 
-enum { GR_APPLY = 0, GR_PROJECT = 1 };
+// APPLY: grid y.  PROJECT: step 8 from r and v_old, grid v_new - v_old.  FRESH: every block
+// active, step 8 from r alone, grid v_new.
+enum { GR_APPLY = 0, GR_PROJECT = 1, GR_FRESH = 2 };
 
 // A gridding unit: one tile and the range [b, e) of idx[] listing the items that fall in
 // it (x = tile, y = b, z = e, w = their visibility count).
@@ -278,7 +283,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
   auto next_active = [&](int q, int end) {
-    while (q < end && mask != nullptr && mask[items[q].x] == 0) ++q;
+    while (q < end && MODE != GR_FRESH && mask != nullptr && mask[items[q].x] == 0) ++q;
     return q;
   };
   // operands of the current item, and the raw loads of the next one
@@ -293,6 +298,8 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
         rc[k] = coord[m];
         if (MODE == GR_APPLY) {
           ra[k] = y[m];
+        } else if (MODE == GR_FRESH) {
+          rb[k] = e[m];
         } else {
           ra[k] = v[m];
           rb[k] = e[m];
@@ -302,7 +309,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   };
   // values (with the dual update of step 8) and the bound into red_b[buf]
   auto finish = [&](const Item& it, int buf) {
-    const float sh = MODE == GR_PROJECT ? shrink[it.x] : 0.f;
+    const float sh = MODE != GR_APPLY ? shrink[it.x] : 0.f;
     float babs = 0.f;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
@@ -311,8 +318,12 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
         const int m = it.z + s;
         if (MODE == GR_APPLY) {
           val[k] = ra[k];
+        } else if (MODE == GR_FRESH) {
+          const float2 vn = make_float2(rb[k].x * sh, rb[k].y * sh);
+          v[m] = vn;
+          val[k] = vn;
         } else {
-          const float2 vn = make_float2((ra[k].x + rb[k].x) * sh, (ra[k].y + rb[k].y) * sh);
+          const float2 vn = make_float2(rb[k].x * sh, rb[k].y * sh);
           v[m] = vn;
           val[k] = make_float2(vn.x - ra[k].x, vn.y - ra[k].y);
         }
@@ -360,7 +371,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
     int q = un.y, buf = 0;
     Item it = items[q];
     load_raw(it);
-    if (mask != nullptr && mask[it.x] == 0) {
+    if (MODE != GR_FRESH && mask != nullptr && mask[it.x] == 0) {
       q = next_active(q + 1, un.z);
       if (q < un.z) {
         it = items[q];
@@ -653,38 +664,47 @@ int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, 
   return RI_OK;
 }
 
+namespace {
+
+// Degridding over the plan's units (in XCD order, see create_plan).
+template <int T, int MODE>
+int degrid_batched_t(const Plan& p, const float2* grid, float2* out, const float2* y, const float2* v,
+                     double* part, const uint8_t* mask, hipStream_t s) {
+  if (p.n_dunits > 0) {
+    hipLaunchKernelGGL((k_degrid<T, MODE>), dim3(wgs_for(p, p.n_dunits)), dim3(GT), 0, s, p.dunits, p.n_dunits,
+                       p.titems, mask, p.coord, grid, p.K, p.tpa, p.poly, out, y, v, part);
+    RI_LAUNCH_CHECK();
+  }
+  return RI_OK;
+}
+
+template <int MODE>
+int degrid_batched(const Plan& p, const float2* grid, float2* out, const float2* y, const float2* v, double* part,
+                   const uint8_t* mask, hipStream_t s) {
+  switch (p.tile) {
+    case 16: return degrid_batched_t<16, MODE>(p, grid, out, y, v, part, mask, s);
+    case 32: return degrid_batched_t<32, MODE>(p, grid, out, y, v, part, mask, s);
+    case 64: return degrid_batched_t<64, MODE>(p, grid, out, y, v, part, mask, s);
+    default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
+  }
+}
+
+}  // namespace
+
 int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* mask, hipStream_t s) {
   if (p.dde.on()) return dde_degrid(p, p.dunits, p.n_dunits, p.titems, mask, grid, y, nullptr, nullptr, nullptr, s);
-  const dim3 grid_dim(wgs_for(p, p.n_dunits));
-#define ARGS p.dunits, p.n_dunits, p.titems, mask, p.coord, grid, p.K, p.tpa, p.poly, y, \
-             (const float2*)nullptr, (const float2*)nullptr, (double*)nullptr
-  RI_TILE_DISPATCH(k_degrid, DG_APPLY)
-#undef ARGS
-  RI_LAUNCH_CHECK();
-  return RI_OK;
+  return degrid_batched<DG_APPLY>(p, grid, y, nullptr, nullptr, nullptr, mask, s);
 }
 
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
                     const uint8_t* mask, hipStream_t s) {
   if (p.dde.on()) return dde_degrid(p, p.dunits, p.n_dunits, p.titems, mask, grid, e, y, v, p.item_part, s);
-  const dim3 grid_dim(wgs_for(p, p.n_dunits));
-#define ARGS p.dunits, p.n_dunits, p.titems, mask, p.coord, grid, p.K, p.tpa, p.poly, e, y, v, \
-             p.item_part
-  RI_TILE_DISPATCH(k_degrid, DG_RESIDUAL)
-#undef ARGS
-  RI_LAUNCH_CHECK();
-  return RI_OK;
+  return degrid_batched<DG_RESIDUAL>(p, grid, e, y, v, p.item_part, mask, s);
 }
 
 int degrid_norms(const Plan& p, const float2* grid, const float2* y, const float2* v, double* part, hipStream_t s) {
   if (p.dde.on()) return dde_degrid(p, p.dunits, p.n_dunits, p.titems, nullptr, grid, nullptr, y, v, part, s);
-  const dim3 grid_dim(wgs_for(p, p.n_dunits));
-#define ARGS p.dunits, p.n_dunits, p.titems, (const uint8_t*)nullptr, p.coord, grid, p.K, p.tpa, p.poly, \
-             (float2*)nullptr, y, v, part
-  RI_TILE_DISPATCH(k_degrid, DG_NORMS)
-#undef ARGS
-  RI_LAUNCH_CHECK();
-  return RI_OK;
+  return degrid_batched<DG_NORMS>(p, grid, nullptr, y, v, part, nullptr, s);
 }
 
 int degrid_residual_block(const Plan& p, int block, const float2* grid, const float2* y, const float2* v,
@@ -721,6 +741,12 @@ int grid_project(const Plan& p, const float2* e, float2* v, const float* shrink,
     return dde_grid(p, p.dde.tunits, p.dde.n_tunits, p.titems, mask, nullptr, e, v, shrink, true, false, s);
   return grid_units<GR_PROJECT>(p, true, p.units, p.n_units, p.titems, mask, grid, nullptr, e, v, shrink, s,
                                 false);
+}
+
+int grid_project_all(const Plan& p, const float2* r, float2* v, const float* shrink, float2* grid, hipStream_t s) {
+  if (p.dde.on()) return fail(RI_EINVAL, "grid_project_all: the DDE kernels update the running sum instead");
+  return grid_units<GR_FRESH>(p, true, p.units, p.n_units, p.titems, nullptr, grid, nullptr, r, v, shrink, s, false,
+                              true);
 }
 
 int grid_halo(const Plan& p, float2* grid, hipStream_t s) {

@@ -1,10 +1,10 @@
 // Algorithm 1, randomised forward-backward primal-dual, one iteration per call.
 //
-// Data-fidelity branch (steps 4-11): b~ = F Z x~; for active blocks e = G_i b_i - y_i with
-// FP64 block norms; v_i <- (v_i + e) max(0, 1 - eps_i / ||v_i + e||); the change of
-// G_i^dagger v_i is added to the running sum sum_i M_i^dagger v~_i, which therefore holds
-// the latest v~_i of active blocks and the kept v~_i of inactive ones (step 11); then
-// g = Re Z^dagger F^dagger (that sum).
+// Data-fidelity branch (steps 4-11): b~ = F Z x~; for active blocks r = v_i + G_i b_i - y_i
+// with FP64 block norms; v_i <- r max(0, 1 - eps_i / ||r||); the change of G_i^dagger v_i is
+// added to the running sum sum_i M_i^dagger v~_i, which therefore holds the latest v~_i of
+// active blocks and the kept v~_i of inactive ones (step 11) (with every block active the
+// sum is rebuilt from the new v instead); then g = Re Z^dagger F^dagger (that sum).
 // Sparsity branch (steps 13-14): s <- clip(s + Psi^dagger x~, -alpha, alpha), then
 // s~ = Psi s.
 // The two branches depend only on x~ of the previous iteration (the paper runs them
@@ -12,8 +12,8 @@
 // forward FFT and joins before the last kernel, the adjoint row pass, which applies the
 // elementwise steps 17-18 to g as it produces it (g is never stored).
 //
-// The running sum is kept in FP32 and updated by differences; ri_pd_refresh (and setting
-// V) rebuilds it from the stored v, bounding accumulated rounding.
+// The running sum is kept in FP32 and updated by differences when blocks are masked;
+// ri_pd_refresh (and setting V) rebuilds it from the stored v, bounding accumulated rounding.
 #include <algorithm>
 #include <cmath>
 #include <mutex>
@@ -31,7 +31,7 @@ struct ri_pd_s {
   float alpha = 0.f;
   float2* y = nullptr;
   float2* v = nullptr;
-  float2* e = nullptr;
+  float2* e = nullptr;     // r = v + G b - y of the last step's active blocks
   float* x = nullptr;
   float* xt = nullptr;
   float* s = nullptr;
@@ -275,7 +275,12 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
   RI_STAGE(P, RI_STAGE_DEGRID, stream,
            ri::degrid_residual(p, p.grid, P->y, P->v, P->e, mask, stream));
   RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, mask, P->stats, stats, stream, P->eps, P->shrink));
-  RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project(p, P->e, P->v, P->shrink, mask, P->sum, stream));
+  // every block active (no mask): the sum is rebuilt from the new duals, reading r only;
+  // otherwise the active blocks' changes are added to it
+  if (mask == nullptr && !p.dde.on())
+    RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project_all(p, P->e, P->v, P->shrink, P->sum, stream));
+  else
+    RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project(p, P->e, P->v, P->shrink, mask, P->sum, stream));
   RI_STAGE(P, RI_STAGE_GRID_HALO, stream, ri::grid_halo(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
   // join, then the adjoint row pass with steps 17-18 fused into its output
@@ -526,10 +531,9 @@ int ri_pd_weighted(ri_pd P, int* out) {
 }
 
 int ri_pd_step_vjp(ri_pd P, const uint8_t* mask, const float* x_new, const float* s_new, const float* v_new,
-                   const float* v_old, const float* e, const double* stats, float* xbar, float* xtbar,
-                   float* sbar, float* vbar, double* pgrad, hipStream_t stream) {
-  if (!P || !mask || !x_new || !s_new || !v_new || !v_old || !e || !stats || !xbar || !xtbar || !sbar || !vbar ||
-      !pgrad)
+                   const float* r, const double* stats, float* xbar, float* xtbar, float* sbar, float* vbar,
+                   double* pgrad, hipStream_t stream) {
+  if (!P || !mask || !x_new || !s_new || !v_new || !r || !stats || !xbar || !xtbar || !sbar || !vbar || !pgrad)
     return fail(RI_EINVAL, "NULL argument");
   const ri::Plan& p = *P->plan;
   const ri::Sara& S = *P->sara;
@@ -547,8 +551,7 @@ int ri_pd_step_vjp(ri_pd P, const uint8_t* mask, const float* x_new, const float
     RI_TRY(ri::dev_alloc(&P->vj_coef, 2 * size_t(p.d)));
   }
   const double tau = P->prm.tau, sigma = P->prm.sigma, vs = P->prm.varsigma;
-  const float2* vo = reinterpret_cast<const float2*>(v_old);
-  const float2* ee = reinterpret_cast<const float2*>(e);
+  const float2* rr = reinterpret_cast<const float2*>(r);
   float2* vb = reinterpret_cast<float2*>(vbar);
   // steps 17-18
   RI_TRY(ri::vjp_primal(N, x_new, xbar, xtbar, P->vj_z, stream));
@@ -561,8 +564,7 @@ int ri_pd_step_vjp(ri_pd P, const uint8_t* mask, const float* x_new, const float
   RI_TRY(ri::psi_apply(S, sbar, xtbar, stream));
   // steps 5-11 (through g = Re Phi^dagger v'), then x~bar += Re Phi_A^dagger rbar
   RI_TRY(ri::phi_apply(p, P->vj_z, reinterpret_cast<float*>(P->vj_phiz), nullptr, stream));
-  RI_TRY(ri::vjp_ball(p, mask, vb, P->vj_phiz, float(-tau * vs), vo, ee, stats, P->eps, P->vj_part, P->vj_coef,
-                      stream));
+  RI_TRY(ri::vjp_ball(p, mask, vb, P->vj_phiz, float(-tau * vs), rr, stats, P->eps, P->vj_part, P->vj_coef, stream));
   RI_TRY(ri::phi_adj_apply(p, vbar, P->vj_g, mask, stream));
   return ri::axpy(N, 1.f, P->vj_g, xtbar, stream);
 }

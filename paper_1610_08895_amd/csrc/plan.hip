@@ -299,6 +299,29 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   }
   std::stable_sort(dunits.begin(), dunits.end(), [](const int4& l, const int4& r) { return l.w > r.w; });
   p.n_dunits = int(dunits.size());
+  {
+    // XCD-aware order of the degridding units.  The dispatcher deals consecutive
+    // workgroups round-robin over the eight XCDs, and a dense tile has several units, each
+    // staging the same tile and reach: the tiles are dealt to the XCDs in density order and
+    // all units of a tile are placed at positions equal modulo 8, so that their stagings hit
+    // the one XCD's L2.  Gaps (XCDs with fewer units) hold empty units.
+    constexpr int NX = 8;
+    std::vector<std::vector<int4>> per_xcd(NX);
+    std::vector<int> tile_xcd(p.n_tiles, -1);
+    int next = 0;
+    for (int k = 0; k < p.n_dunits; ++k) {
+      int& x = tile_xcd[dunits[k].x];
+      if (x < 0) x = next++ % NX;
+      per_xcd[x].push_back(dunits[k]);
+    }
+    size_t L = 0;
+    for (const auto& v : per_xcd) L = std::max(L, v.size());
+    std::vector<int4> ordered(L * NX, make_int4(0, 0, 0, 0));
+    for (int x = 0; x < NX; ++x)
+      for (size_t j = 0; j < per_xcd[x].size(); ++j) ordered[j * NX + x] = per_xcd[x][j];
+    dunits.swap(ordered);
+    p.n_dunits = int(dunits.size());
+  }
   p.bunit_off_host.assign(size_t(d) + 1, 0);
   for (int i = 0; i < d; ++i) {
     p.bunit_off_host[i] = int(bunits.size());

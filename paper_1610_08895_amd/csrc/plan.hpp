@@ -165,9 +165,9 @@ int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* ma
 // grid = G^dagger y for the active blocks (operator form; the whole grid is written, tiles
 // without visibilities set to zero).
 int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid, hipStream_t s);
-// PD residual pass: e = G b - y, r = v + e; stats[2i] = ||r_i||^2, stats[2i+1] = ||e_i||^2 for the
-// blocks whose items are processed (per-item partial sums, then a per-block reduction).
-// All items (those of inactive blocks skipped), or the items of one block.
+// PD residual pass: r = v + G b - y stored in r_out; stats[2i] = ||r_i||^2, stats[2i+1] =
+// ||G_i b_i - y_i||^2 for the blocks whose items are processed (per-item partial sums, then
+// a per-block reduction).  All items (those of inactive blocks skipped), or one block's.
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
                     const uint8_t* mask, hipStream_t s);
 // The norms of degrid_residual over all items, without storing e, into the given partials
@@ -175,12 +175,14 @@ int degrid_residual(const Plan& p, const float2* grid, const float2* y, const fl
 int degrid_norms(const Plan& p, const float2* grid, const float2* y, const float2* v, double* part, hipStream_t s);
 int degrid_residual_block(const Plan& p, int block, const float2* grid, const float2* y, const float2* v,
                           float2* e, hipStream_t s);
-// PD projection pass: v_new = (v + e) shrink_i (shrink from block_stats); grid += G^dagger
-// (v_new - v); v = v_new, for the active blocks (tile interiors; grid_halo must follow) or
-// for one block (complete).
+// PD projection pass: v_new = r shrink_i (r from degrid_residual, shrink from block_stats);
+// grid += G^dagger (v_new - v); v = v_new, for the active blocks (tile interiors; grid_halo
+// must follow) or for one block.  grid_project_all, with every block active: v = v_new and
+// grid = G^dagger v_new (tile interiors stored; grid_halo must follow); not with DDEs.
 int grid_project(const Plan& p, const float2* e, float2* v, const float* shrink, const uint8_t* mask, float2* grid,
                  hipStream_t s);
 // Adds the tile halos left by grid_project (which stores them) into the grid.
+int grid_project_all(const Plan& p, const float2* r, float2* v, const float* shrink, float2* grid, hipStream_t s);
 int grid_halo(const Plan& p, float2* grid, hipStream_t s);
 // y = Phi x over the blocks with mask[i] != 0 (mask may be null: all); x = Re Phi^dagger y.
 // y is complex interleaved (M), x real (n*n); both use the plan's work grid.

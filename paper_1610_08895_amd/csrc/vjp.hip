@@ -84,20 +84,20 @@ __global__ __launch_bounds__(VT) void k_axpy(int n, float a, const float* __rest
   for (int k = blockIdx.x * VT + threadIdx.x; k < n; k += gridDim.x * VT) y[k] += a * x[k];
 }
 
-// part[i * nch + ch] = sum over chunk ch of block i of r^T u, u = vbar + c phiz, r = v_old + e
+// part[i * nch + ch] = sum over chunk ch of block i of r^T u, u = vbar + c phiz
 __global__ __launch_bounds__(VT) void k_ball_dot(const int64_t* __restrict__ off, const uint8_t* __restrict__ mask,
                                                  const float2* __restrict__ vbar, const float2* __restrict__ phiz,
-                                                 float c, const float2* __restrict__ v_old,
-                                                 const float2* __restrict__ e, int nch, double* __restrict__ part) {
+                                                 float c, const float2* __restrict__ r, int nch,
+                                                 double* __restrict__ part) {
   __shared__ double red[VT / 64];
   const int i = blockIdx.y, ch = blockIdx.x;
   if (mask[i] == 0) return;
   const int64_t lo = off[i] + int64_t(ch) * BALL_CHUNK, hi = min(off[i + 1], lo + BALL_CHUNK);
   double acc = 0.0;
   for (int64_t m = lo + threadIdx.x; m < hi; m += VT) {
-    const float2 vb = vbar[m], pz = phiz[m], vo = v_old[m], ee = e[m];
+    const float2 vb = vbar[m], pz = phiz[m], rr = r[m];
     const double ux = double(vb.x) + double(c) * pz.x, uy = double(vb.y) + double(c) * pz.y;
-    acc += (double(vo.x) + ee.x) * ux + (double(vo.y) + ee.y) * uy;
+    acc += double(rr.x) * ux + double(rr.y) * uy;
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x / 64] = acc;
@@ -135,8 +135,7 @@ __global__ void k_ball_coef(int d, const int64_t* __restrict__ off, const uint8_
 
 __global__ __launch_bounds__(VT) void k_ball_apply(const int64_t* __restrict__ off, const uint8_t* __restrict__ mask,
                                                    float2* __restrict__ vbar, const float2* __restrict__ phiz, float c,
-                                                   const float2* __restrict__ v_old, const float2* __restrict__ e,
-                                                   const double* __restrict__ coef) {
+                                                   const float2* __restrict__ r, const double* __restrict__ coef) {
   const int i = blockIdx.y, ch = blockIdx.x;
   const int64_t lo = off[i] + int64_t(ch) * BALL_CHUNK, hi = min(off[i + 1], lo + BALL_CHUNK);
   const float a = float(coef[2 * i]), b = float(coef[2 * i + 1]);
@@ -146,9 +145,9 @@ __global__ __launch_bounds__(VT) void k_ball_apply(const int64_t* __restrict__ o
     const float2 u = make_float2(vb.x + c * pz.x, vb.y + c * pz.y);
     float2 out = make_float2(a * u.x, a * u.y);
     if (active) {
-      const float2 vo = v_old[m], ee = e[m];
-      out.x += b * (vo.x + ee.x);
-      out.y += b * (vo.y + ee.y);
+      const float2 rr = r[m];
+      out.x += b * rr.x;
+      out.y += b * rr.y;
     }
     vbar[m] = out;
   }
@@ -192,16 +191,16 @@ int ball_chunks(const Plan& p) {
   return int((mx + BALL_CHUNK - 1) / BALL_CHUNK);
 }
 
-int vjp_ball(const Plan& p, const uint8_t* mask, float2* vbar, const float2* phiz, float c, const float2* v_old,
-             const float2* e, const double* stats, const double* eps, double* part, double* coef, hipStream_t s) {
+int vjp_ball(const Plan& p, const uint8_t* mask, float2* vbar, const float2* phiz, float c, const float2* r,
+             const double* stats, const double* eps, double* part, double* coef, hipStream_t s) {
   const int nch = ball_chunks(p);
   const dim3 g(nch, p.d);
-  hipLaunchKernelGGL(k_ball_dot, g, dim3(VT), 0, s, p.block_off, mask, vbar, phiz, c, v_old, e, nch, part);
+  hipLaunchKernelGGL(k_ball_dot, g, dim3(VT), 0, s, p.block_off, mask, vbar, phiz, c, r, nch, part);
   RI_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_ball_coef, dim3((p.d + 255) / 256), dim3(256), 0, s, p.d, p.block_off, mask, stats, eps, part,
                      nch, coef);
   RI_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_ball_apply, g, dim3(VT), 0, s, p.block_off, mask, vbar, phiz, c, v_old, e, coef);
+  hipLaunchKernelGGL(k_ball_apply, g, dim3(VT), 0, s, p.block_off, mask, vbar, phiz, c, r, coef);
   RI_LAUNCH_CHECK();
   return RI_OK;
 }

@@ -22,7 +22,8 @@ int axpy(int n, float a, const float* x, float* y, hipStream_t s);
 int ball_chunks(const Plan& p);
 // vbar <- step-8 VJP of u = vbar + c phiz per block (see vjp.hip); part: d * ball_chunks,
 // coef: 2 d doubles of scratch.
-int vjp_ball(const Plan& p, const uint8_t* mask, float2* vbar, const float2* phiz, float c, const float2* v_old,
-             const float2* e, const double* stats, const double* eps, double* part, double* coef, hipStream_t s);
+// r: v_old + G b - y of the step (RI_PD_E after it).
+int vjp_ball(const Plan& p, const uint8_t* mask, float2* vbar, const float2* phiz, float c, const float2* r,
+             const double* stats, const double* eps, double* part, double* coef, hipStream_t s);
 
 }  // namespace ri

@@ -220,7 +220,7 @@ class PD:
         L.check(L.load().ri_pd_residual(self._h, _dev(out, torch.float64, (self.plan.d, 2), "out"), _stream()))
         return out
 
-    def step_vjp(self, mask, x_new, s_new, v_new, v_old, e, stats, xbar, xtbar, sbar, vbar, pgrad):
+    def step_vjp(self, mask, x_new, s_new, v_new, r, stats, xbar, xtbar, sbar, vbar, pgrad):
         """Reverse sweep of one step (ri_pd_step_vjp): the adjoints xbar, xtbar, sbar, vbar
         are updated in place from after the step to before it; pgrad (2 FP64) accumulates
         the step's dL/dtau and dL/dsigma."""
@@ -228,7 +228,7 @@ class PD:
         L.check(L.load().ri_pd_step_vjp(
             self._h, _mask(mask, d), _dev(x_new, torch.float32, (n, n), "x_new"),
             _dev(s_new, torch.float32, (b, n, n), "s_new"), _dev(v_new, torch.complex64, (M,), "v_new"),
-            _dev(v_old, torch.complex64, (M,), "v_old"), _dev(e, torch.complex64, (M,), "e"),
+            _dev(r, torch.complex64, (M,), "r"),
             _dev(stats, torch.float64, (d, 2), "stats"), _dev(xbar, torch.float32, (n, n), "xbar"),
             _dev(xtbar, torch.float32, (n, n), "xtbar"), _dev(sbar, torch.float32, (b, n, n), "sbar"),
             _dev(vbar, torch.complex64, (M,), "vbar"), _dev(pgrad, torch.float64, (2,), "pgrad"), _stream()))

@@ -72,7 +72,7 @@ class Solver:
         self._mask_host = np.ones(plan.d, np.uint8)  # what mask_dev holds
         self.stats_dev = torch.zeros(plan.d, 2, dtype=torch.float64, device="cuda")
         self.res_dev = torch.zeros(plan.d, 2, dtype=torch.float64, device="cuda")
-        self._graph = None
+        self._graphs = {}
 
     def initial_energy(self):
         """Eq. 13 at x = 0 (the residual is the data itself)."""
@@ -96,10 +96,12 @@ class Solver:
         self.pd.iteration = it
         return g
 
-    def capture(self):
-        """Capture one iteration (reading self.mask_dev) into a graph for replay."""
-        self._graph = self._capture(lambda: self.pd.step(self.mask_dev, self.stats_dev))
-        return self._graph
+    def capture(self, all_blocks=False):
+        """Capture one iteration into a graph for replay: reading self.mask_dev, or with
+        every block active (no mask: the step rebuilds the grid sum from the new duals)."""
+        mask = None if all_blocks else self.mask_dev
+        self._graphs[all_blocks] = self._capture(lambda: self.pd.step(mask, self.stats_dev))
+        return self._graphs[all_blocks]
 
     def _set_mask(self, mask_host):
         m = np.ones(self.plan.d, np.uint8) if mask_host is None else np.ascontiguousarray(mask_host, np.uint8)
@@ -108,16 +110,19 @@ class Solver:
             self._mask_host = m.copy()
 
     def step(self, mask_host=None, graph=False, plain=False):
-        self._set_mask(mask_host)
+        """One iteration; mask_host None means every block active."""
+        every = mask_host is None
+        if not every:
+            self._set_mask(mask_host)
         if plain:
-            self.pd.step_plain(self._mask_host, self.stats_dev)
+            self.pd.step_plain(None if every else self._mask_host, self.stats_dev)
         elif graph:
-            if self._graph is None:
-                self.capture()
-            self._graph.replay()
+            if every not in self._graphs:
+                self.capture(every)
+            self._graphs[every].replay()
             self.pd.iteration = self.pd.iteration + 1
         else:
-            self.pd.step(self.mask_dev, self.stats_dev)
+            self.pd.step(None if every else self.mask_dev, self.stats_dev)
 
     def prepare(self, iterations, schedule: Schedule = Schedule(), uniforms=None, masks=None, graph=False,
                 seed=0, reweight: Reweight = None):
@@ -250,7 +255,7 @@ class BatchedRun:
                                         u=uniforms if masks is None else None, masks=masks, p_fixed=p_fixed,
                                         c0=solver.initial_energy() if adaptive else None, n_nodes=schedule.n_nodes,
                                         p_min=schedule.p_min, p_max=schedule.p_max)
-        self.mask = self.sched.mask if self.sched is not None else torch.ones(d, dtype=torch.uint8, device="cuda")
+        self.mask = self.sched.mask if self.sched is not None else None  # None: every block, no draw
         self.flags = SCHED_DRAW | ((SCHED_UPDATE | SCHED_ADAPTIVE) if adaptive else 0)
         if self.K:
             solver.pd.residual(solver.res_dev)  # its scratch is allocated outside any capture

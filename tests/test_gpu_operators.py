@@ -267,3 +267,26 @@ def test_grid_point_carry_and_band_edge_coordinates(R):
     sel = np.flatnonzero((uv[:, 0] == np.float32(-np.pi)) | (uv[:, 1] == np.float32(-np.pi)))
     assert sel.size > 0
     assert rel_l2(y[sel], meas.phi(x)[sel]) < TOL
+
+
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_light_units_match_oracle(R, tile):
+    """Sparse coverage where most tiles hold fewer than 256 visibilities from several blocks
+    (units with few items, degridding units in XCD order with gaps); Phi, Phi^dagger and
+    masked Phi^dagger against the oracle."""
+    n, M, d = 128, 3000, 6
+    rng = np.random.default_rng(tile)
+    x = synth.sky(n, 5, 10, rng)
+    uv = rng.uniform(-np.pi, np.pi, (M, 2)).astype(np.float32)  # spread over every tile
+    uvs, off, _ = synth.partition(uv, d, "equal")
+    plan = R.Plan(n, uvs, off, tile=tile)
+    order = plan.order()
+    meas = Measurement(uvs, off, (n, n))
+    y = to_user(plan.phi(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy(), order)
+    assert rel_l2(y, meas.phi(x)) < TOL
+    w = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    wt = torch.tensor(to_plan(w, order), dtype=torch.complex64, device="cuda")
+    assert rel_l2(plan.phi_adj(wt).cpu().numpy(), meas.phi_adj_real(w)) < TOL
+    mask = np.array([1, 0, 1, 1, 0, 1], np.uint8)
+    xm = plan.phi_adj(wt, mask=torch.tensor(mask, device="cuda")).cpu().numpy()
+    assert rel_l2(xm, meas.phi_adj_real(w, blocks=np.flatnonzero(mask))) < TOL

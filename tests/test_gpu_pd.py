@@ -90,6 +90,36 @@ def test_iterations_match_oracle_with_random_masks(R, plain, tune):
             assert rel_l2(vg, vo) < 1e-4 * (1 + t)
 
 
+def test_light_units_in_the_step_match_oracle(R):
+    """Sparse coverage (most tiles light, several blocks per tile) through masked and
+    all-blocks steps of Algorithm 1 against the oracle."""
+    n, M, d = 128, 4000, 6
+    rng = np.random.default_rng(21)
+    x = synth.sky(n, 5, 10, rng)
+    uvs, off, _ = synth.partition(rng.uniform(-np.pi, np.pi, (M, 2)).astype(np.float32), d, "equal")
+    meas = Measurement(uvs, off, (n, n))
+    osara = OSara(n)
+    y0 = meas.phi(x)
+    sig = synth.noise_sigma(y0, 20.0)
+    y = y0 + synth.complex_noise(M, sig, rng)
+    eps = synth.l2_ball_radii(off, sig)
+    prm = opd.default_params(3.0, 60.0)
+    plan = R.Plan(n, uvs, off)
+    order = plan.order()
+    pdg = R.PD(plan, R.Sara(n), torch.tensor(to_plan(y, order), dtype=torch.complex64, device="cuda"), eps,
+               prm.tau, prm.sigma, prm.varsigma, prm.kappa, 3.0, 60.0)
+    yb = opd.split_blocks(meas, y)
+    st = opd.init_state(meas, osara)
+    for t in range(8):
+        mask = (rng.uniform(size=d) < 0.6).astype(np.uint8) if t % 2 else np.ones(d, np.uint8)
+        opd.iteration(meas, osara, yb, eps, prm, st, mask.astype(bool))
+        pdg.step(None if t % 2 == 0 else torch.tensor(mask, device="cuda"))
+        assert rel_l2(pdg.get(0).cpu().numpy(), st.x) < 1e-4 * (1 + t), t
+        vo = np.concatenate(st.v)
+        if np.linalg.norm(vo) > 0:
+            assert rel_l2(to_user(pdg.get(3).cpu().numpy(), order), vo) < 1e-4 * (1 + t), t
+
+
 def test_inactive_blocks_keep_their_duals_bitwise(R):
     S = _setup(R, n=64, M=6000, d=4, seed=5)
     pdg = _pd(R, S)
@@ -114,6 +144,32 @@ def test_batched_equals_plain(R):
         b.step_plain(mask)
     assert rel_l2(a.get(0).cpu().numpy(), b.get(0).cpu().numpy()) < 1e-5
     assert rel_l2(a.get(3).cpu().numpy(), b.get(3).cpu().numpy()) < 1e-5
+
+
+@pytest.mark.parametrize("tune", [{}, {"slice_vis": 150, "bin": 64}])
+def test_all_blocks_rebuild_equals_masked_update(R, tune):
+    """A step without a mask (every block active: the grid sum rebuilt from the new duals,
+    reading r only) and a step with an all-ones mask (the changes added to the kept sum)
+    give the same iterates, also with tiles split into slices; both match the oracle."""
+    S = _setup(R, n=64, M=8000, d=5, scheme="lognormal", seed=12, **tune)
+    a, b = _pd(R, S), _pd(R, S)
+    ones = torch.ones(5, dtype=torch.uint8, device="cuda")
+    sa = torch.zeros(5, 2, dtype=torch.float64, device="cuda")
+    sb = torch.zeros_like(sa)
+    meas, osara = S["meas"], S["osara"]
+    yb = opd.split_blocks(meas, S["y"])
+    st = opd.init_state(meas, osara)
+    for t in range(10):
+        a.step(None, sa)
+        b.step(ones, sb)
+        opd.iteration(meas, osara, yb, S["eps"], S["prm"], st, np.ones(5, bool))
+        # the two differ by the FP32 rounding of the kept sum's updates only
+        assert rel_l2(a.get(0).cpu().numpy(), b.get(0).cpu().numpy()) < 1e-5, t
+        assert rel_l2(a.get(3).cpu().numpy(), b.get(3).cpu().numpy()) < 1e-5, t
+        assert torch.allclose(sa, sb, rtol=1e-5)
+        assert rel_l2(a.get(0).cpu().numpy(), st.x) < 1e-4 * (1 + t), t
+        assert rel_l2(b.get(0).cpu().numpy(), st.x) < 1e-4 * (1 + t), t
+    assert rel_l2(a.get(5).cpu().numpy(), b.get(5).cpu().numpy()) < 1e-5
 
 
 def test_snr_parity_small_workload(R):
