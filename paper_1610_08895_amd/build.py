@@ -34,9 +34,10 @@ COMMON = [
 ]
 
 
-# Per-source extra flags.  The gridding kernels round with floor(fma(w, t, c)), which becomes
-# one v_cvt_flr_i32_f32 only when NaN and infinity need not be honoured; every value they
-# round is finite.  Later flags override COMMON's.
+# Per-source extra flags.  Every value the gridding kernels handle is finite, so NaN and
+# infinity need not be honoured: floor(fma(w, t, c)) then becomes one v_cvt_flr_i32_f32 (the
+# DDE kernels' rounding) and fmaxf needs no quieting of its operands (the bounds of the
+# fixed-point scale).  Later flags override COMMON's.
 EXTRA = {"gridding.hip": ["-fno-honor-nans", "-fno-honor-infinities"],
          # the DDE kernels round the same way, and dispatch through templated lambdas (C++20)
          "dde.hip": ["-fno-honor-nans", "-fno-honor-infinities", "-std=c++20"]}

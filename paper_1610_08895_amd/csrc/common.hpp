@@ -117,4 +117,15 @@ __device__ __forceinline__ T wave_sum(T v) {
   return lane63(v);
 }
 
+// Maximum over the 64 lanes of a wavefront (all active, values >= 0), the same lane moves.
+__device__ __forceinline__ float wave_max(float v) {
+  v = fmaxf(v, lane_move<0xb1, 0xf>(v));
+  v = fmaxf(v, lane_move<0x4e, 0xf>(v));
+  v = fmaxf(v, lane_move<0x141, 0xf>(v));
+  v = fmaxf(v, lane_move<0x140, 0xf>(v));
+  v = fmaxf(v, lane_move<0x142, 0xa>(v));
+  v = fmaxf(v, lane_move<0x143, 0xc>(v));
+  return lane63(v);
+}
+
 }  // namespace ri

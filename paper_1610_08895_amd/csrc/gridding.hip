@@ -228,22 +228,25 @@ __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ 
 // active, step 8 from r alone, grid v_new.
 enum { GR_APPLY = 0, GR_PROJECT = 1, GR_FRESH = 2 };
 
+// Rounding of a float t with |t| < 2^22 to an integer by adding 1.5 * 2^23 (see below).
+constexpr float ROUND_BIAS = 12582912.0f;
+constexpr unsigned long long ROUND_BIAS_BITS = 0x4B4000004B400000ull;
+
 // A gridding unit: one tile and the range [b, e) of idx[] listing the items that fall in
 // it (x = tile, y = b, z = e, w = their visibility count).
 //
 // Per item the contributions are accumulated exactly in LDS with 64-bit integer atomics
 // (LDS integer atomics are an order of magnitude faster than LDS float atomics on this
 // hardware), Re in the low and Im in the high 32 bits of one word: every value is scaled
-// by a power of two 2^E chosen from the item's sum of |Re| + |Im|, which bounds any cell's
-// sum, so each field stays below 2^30 in magnitude.  A contribution (re, im) is added as
-// the 64-bit word re + (im + c) 2^32 with re taken modulo 2^32 in the low half, where c is
-// -1 for the rows whose Re factor has its sign bit set and 0 otherwise (folded into the
-// rounding of im as a copysign of its 0.5 offset): the word then equals re + im' 2^32 exactly
-// with im' = im + c + [re < 0], and since the kernel weights are positive, re < 0 exactly
-// when the row's factor is negative except for products that round to zero, so im' differs
-// from im by at most one unit.  Decoding
-// subtracts the sign-extended low field.  Rounding (to nearest, halves up) is at most
-// 2^-E-1 per contribution for Re and 2^-E-1 + 2^-E for Im.
+// by a power of two 2^E such that the item's sum of |Re| + |Im|, which bounds any cell's
+// sum (the kernel weights are at most 1), stays below 2^30, and each single contribution
+// below 2^22 in magnitude.  A contribution t = w x is rounded to an integer n by one FMA
+// that adds B = 1.5 * 2^23: for |t| < 2^22 the result lies in [2^23, 2^24), where floats are
+// the integers, so it is B + n with n = t rounded to nearest (ties to even), and its bit
+// pattern is 0x4B400000 + n.  The word is then (bits of Im) 2^32 + (bits of Re) minus the
+// constant 0x4B4000004B400000, which equals n_re + n_im 2^32 in two's complement (a
+// negative n_re borrows from the high half); decoding subtracts the sign-extended low field.
+// Rounding is at most 2^-E-1 per contribution.
 //
 // Two integer tiles alternate between items: while item q is accumulated into one, the
 // cells of item q-1's footprint box are folded out of the other (and cleared) into FP32
@@ -279,7 +282,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   constexpr int NWV = GGT / 64;
   constexpr int NC = (TW * TW + GGT - 1) / GGT;  // region cells per thread
   __shared__ unsigned long long acci[2][TW * TP];
-  __shared__ float red_b[2][NWV];
+  __shared__ float red_b[2][NWV], red_m[2][NWV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
   auto next_active = [&](int q, int end) {
@@ -307,10 +310,10 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
       }
     }
   };
-  // values (with the dual update of step 8) and the bound into red_b[buf]
+  // values (with the dual update of step 8) and the bounds into red_b[buf], red_m[buf]
   auto finish = [&](const Item& it, int buf) {
     const float sh = MODE != GR_APPLY ? shrink[it.x] : 0.f;
-    float babs = 0.f;
+    float babs = 0.f, bmax = 0.f;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       const int s = threadIdx.x + k * GGT;
@@ -329,10 +332,15 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
         }
         crd[k] = rc[k];
         babs += fabsf(val[k].x) + fabsf(val[k].y);
+        bmax = fmaxf(bmax, fmaxf(fabsf(val[k].x), fabsf(val[k].y)));
       }
     }
     babs = wave_sum(babs);
-    if (lane == 0) red_b[buf][wv] = babs;
+    bmax = wave_max(bmax);
+    if (lane == 0) {
+      red_b[buf][wv] = babs;
+      red_m[buf][wv] = bmax;
+    }
   };
   // this thread's region cells
   float2 acc[NC];
@@ -384,9 +392,12 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
     uint32_t pbox = 0;
     float pinv = 0.f;
     while (q < un.z) {
-      float bound = 0.f;
+      float bound = 0.f, bmax = 0.f;
 #pragma unroll
-      for (int w = 0; w < NWV; ++w) bound += red_b[buf][w];
+      for (int w = 0; w < NWV; ++w) {
+        bound += red_b[buf][w];
+        bmax = fmaxf(bmax, red_m[buf][w]);
+      }
       const uint32_t box = item_box[it.y];
       const int qn = next_active(q + 1, un.z);
       Item itn = make_int4(0, 0, 0, 0);
@@ -394,10 +405,15 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
         itn = items[qn];
         load_raw(itn);
       }
-      // 2^E with bound * 2^E <= 2^30 (bound * 1.0001 guards the bound's own rounding)
-      int ex = 0;
-      if (bound > 0.f) frexpf(bound * 1.0001f, &ex);
-      const float scale = ldexpf(1.f, 30 - ex), inv = ldexpf(1.f, ex - 30);
+      // 2^E with bound * 2^E < 2^30 and bmax * 2^E < 2^22 / 1.001 (the factors guard the
+      // bounds' own rounding, the kernel fit's excess over 1 and the rounding of w x)
+      int ex = 0, exm = 0;
+      if (bound > 0.f) {
+        frexpf(bound * 1.0001f, &ex);
+        frexpf(bmax * 1.001f, &exm);
+      }
+      const int e2 = min(30 - ex, 22 - exm);
+      const float scale = ldexpf(1.f, e2), inv = ldexpf(1.f, -e2);
       if (bound > 0.f) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -412,13 +428,11 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
 #pragma unroll
             for (int r = 0; r < KB_J; ++r) {
               const float tr = wy[r] * vr, ti = wy[r] * vi;
-              const float ci = copysignf(0.5f, tr);  // Im rounding offset with the borrow c
 #pragma unroll
               for (int b = 0; b < KB_J; ++b) {
-                const int ir = int(floorf(fmaf(wx[b], tr, 0.5f))), ii = int(floorf(fmaf(wx[b], ti, ci)));
-                const unsigned long long w64 =
-                    (static_cast<unsigned long long>(static_cast<unsigned>(ii)) << 32) | static_cast<unsigned>(ir);
-                atomicAdd(base + r * TP + b, w64);
+                const unsigned lo = __float_as_uint(fmaf(wx[b], tr, ROUND_BIAS));
+                const unsigned hi = __float_as_uint(fmaf(wx[b], ti, ROUND_BIAS));
+                atomicAdd(base + r * TP + b, ((static_cast<unsigned long long>(hi) << 32) | lo) - ROUND_BIAS_BITS);
               }
             }
           }

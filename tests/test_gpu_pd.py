@@ -14,6 +14,11 @@ from oracle.metrics import snr
 from oracle.power import phi_norm as oracle_phi_norm
 from oracle.wavelets import Sara as OSara
 
+# Relative error of the iterates (x, x~, s, v) against the oracle after t + 1 steps: the
+# FP32 operators add about 1e-6 per step (observed at most 1.4e-6 (1 + t) on the random-mask
+# runs below), which the next steps carry forward, so the bound grows linearly in t.
+STATE_TOL = 1e-5
+
 pytestmark = pytest.mark.gpu
 
 
@@ -63,6 +68,7 @@ def test_iterations_match_oracle_with_random_masks(R, plain, tune):
     st = opd.init_state(meas, osara)
     rng = np.random.default_rng(4)
     stats = torch.zeros(5, 2, dtype=torch.float64, device="cuda")
+    worst = 0.0
     for t in range(15):
         mask = (rng.uniform(size=5) < 0.6).astype(np.uint8)
         if t == 0:
@@ -80,14 +86,15 @@ def test_iterations_match_oracle_with_random_masks(R, plain, tune):
                 assert gst[i] == pytest.approx(ost[i], rel=1e-4), (t, i)
             else:
                 assert np.isnan(gst[i]).all()
-        x = pdg.get(0).cpu().numpy()
-        assert rel_l2(x, st.x) < 1e-4 * (1 + t), t
-        assert rel_l2(pdg.get(1).cpu().numpy(), st.xt) < 1e-4 * (1 + t)
-        assert rel_l2(pdg.get(2).cpu().numpy(), st.s) < 1e-4 * (1 + t)
-        vg = _v_user(pdg, S)
+        errs = [rel_l2(pdg.get(0).cpu().numpy(), st.x), rel_l2(pdg.get(1).cpu().numpy(), st.xt),
+                rel_l2(pdg.get(2).cpu().numpy(), st.s)]
         vo = np.concatenate(st.v)
         if np.linalg.norm(vo) > 0:
-            assert rel_l2(vg, vo) < 1e-4 * (1 + t)
+            errs.append(rel_l2(_v_user(pdg, S), vo))
+        worst = max(worst, max(errs) / (1 + t))
+        for k, e in enumerate(errs):
+            assert e < STATE_TOL * (1 + t), (t, k, e)
+    print(f"worst relative error of x, x~, s, v per iteration: {worst:.2e} x (1 + t)")
 
 
 def test_light_units_in_the_step_match_oracle(R):
@@ -110,14 +117,18 @@ def test_light_units_in_the_step_match_oracle(R):
                prm.tau, prm.sigma, prm.varsigma, prm.kappa, 3.0, 60.0)
     yb = opd.split_blocks(meas, y)
     st = opd.init_state(meas, osara)
+    worst = 0.0
     for t in range(8):
         mask = (rng.uniform(size=d) < 0.6).astype(np.uint8) if t % 2 else np.ones(d, np.uint8)
         opd.iteration(meas, osara, yb, eps, prm, st, mask.astype(bool))
         pdg.step(None if t % 2 == 0 else torch.tensor(mask, device="cuda"))
-        assert rel_l2(pdg.get(0).cpu().numpy(), st.x) < 1e-4 * (1 + t), t
+        errs = [rel_l2(pdg.get(0).cpu().numpy(), st.x)]
         vo = np.concatenate(st.v)
         if np.linalg.norm(vo) > 0:
-            assert rel_l2(to_user(pdg.get(3).cpu().numpy(), order), vo) < 1e-4 * (1 + t), t
+            errs.append(rel_l2(to_user(pdg.get(3).cpu().numpy(), order), vo))
+        worst = max(worst, max(errs) / (1 + t))
+        assert max(errs) < 1e-4 * (1 + t), (t, errs)
+    print(f"worst relative error of x, v per iteration: {worst:.2e} x (1 + t)")
 
 
 def test_inactive_blocks_keep_their_duals_bitwise(R):
@@ -159,6 +170,7 @@ def test_all_blocks_rebuild_equals_masked_update(R, tune):
     meas, osara = S["meas"], S["osara"]
     yb = opd.split_blocks(meas, S["y"])
     st = opd.init_state(meas, osara)
+    worst = 0.0
     for t in range(10):
         a.step(None, sa)
         b.step(ones, sb)
@@ -167,9 +179,12 @@ def test_all_blocks_rebuild_equals_masked_update(R, tune):
         assert rel_l2(a.get(0).cpu().numpy(), b.get(0).cpu().numpy()) < 1e-5, t
         assert rel_l2(a.get(3).cpu().numpy(), b.get(3).cpu().numpy()) < 1e-5, t
         assert torch.allclose(sa, sb, rtol=1e-5)
-        assert rel_l2(a.get(0).cpu().numpy(), st.x) < 1e-4 * (1 + t), t
-        assert rel_l2(b.get(0).cpu().numpy(), st.x) < 1e-4 * (1 + t), t
+        ea, eb = rel_l2(a.get(0).cpu().numpy(), st.x), rel_l2(b.get(0).cpu().numpy(), st.x)
+        worst = max(worst, max(ea, eb) / (1 + t))
+        assert ea < 1e-4 * (1 + t), t
+        assert eb < 1e-4 * (1 + t), t
     assert rel_l2(a.get(5).cpu().numpy(), b.get(5).cpu().numpy()) < 1e-5
+    print(f"worst relative error of x per iteration: {worst:.2e} x (1 + t)")
 
 
 def test_snr_parity_small_workload(R):

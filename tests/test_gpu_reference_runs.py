@@ -77,10 +77,11 @@ def _check_trajectory(label, got, want):
     print(f"{label}: {len(got)} points, worst |dSNR| {worst:.4f} dB, final {got[-1][1]:.4f} dB")
 
 
-@pytest.mark.parametrize("label", ["uniform0.5", "adaptive8"])
-def test_reference_run_256(R, label):
+@pytest.mark.parametrize("label,form", [("uniform0.5", "graph"), ("adaptive8", "eager"), ("uniform0.5", "plain")])
+def test_reference_run_256(R, label, form):
     """256x256, M = 131072, 16 blocks: 500 iterations, uniform p = 0.5 and the Eq. 14
-    schedule, replaying the oracle's masks."""
+    schedule, replaying the oracle's masks; the batched step (graph replay or eager) and the
+    plain per-block form (one set of launches per active block)."""
     from paper_1610_08895_amd.solver import Schedule, Solver
 
     ref = _reference("n256_m128k_d16")
@@ -90,8 +91,11 @@ def test_reference_run_256(R, label):
     T = ref["iterations"]
     assert masks.shape == (T, plan.d)
     sol = Solver(plan, R.Sara(w.n), y_plan, eps, ref["psi_norm"], ref["phi_norm"])
-    hist = sol.run(T, masks=masks, refresh=64, x_true=inp.x_true, snr_every=10, graph=label == "uniform0.5")
-    _check_trajectory(label, hist["snr"], rec["snr"])
+    hist = sol.run(T, masks=masks, refresh=64, x_true=inp.x_true, snr_every=10, graph=form == "graph",
+                   plain=form == "plain")
+    _check_trajectory(f"{label} {form}", hist["snr"], rec["snr"])
+    if form == "plain":
+        return
     if rec["kind"] == "adaptive":
         # Eq. 13-14 at x = 0: the first probabilities the GPU schedule draws
         kw = rec["params"]
