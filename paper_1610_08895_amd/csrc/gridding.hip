@@ -29,10 +29,13 @@
 // read-modify-write (no other workgroup writes it) and stores the reach outside the
 // interior in a per-tile halo patch; a second kernel adds the neighbours' patches into
 // each tile's border cells.  No global atomics are needed, and one launch covers all tiles
-// (densest first).  Inside an item consecutive lanes take consecutive visibilities, which
-// the plan orders so that the 64 of one wavefront spread evenly over the LDS banks of the
-// staged tile.  Items whose values are all zero (a block whose dual did not change) are
-// skipped.
+// (densest first).  Inside an item thread t takes positions t, t + 256, t + 512 and
+// t + 768; the plan puts two visibilities of the same cell into slots (0, 1) or (2, 3) of
+// whole wavefronts where it can, and both kernels then treat them as a pair: the
+// degridding reads each staged value once for both, the gridding adds both contributions
+// with one atomic per tap.  The plan also deals the pairs and the single visibilities of a
+// wavefront evenly over the LDS banks of the staged tile.  Items whose values are all zero
+// (a block whose dual did not change) are skipped.
 #include "plan.hpp"
 
 namespace ri {
@@ -41,7 +44,7 @@ namespace {
 
 constexpr int GT = 256;    // threads per workgroup
 static_assert(GT / 64 == PART_WAVES, "one norm partial per wavefront of a workgroup");
-constexpr int GGT = 256;  // threads per workgroup of the tile gridding
+constexpr int GGT = GRID_LANES;  // threads per workgroup of the tile gridding
 
 // Items base .. base + count - 1.
 struct ItemSource {
@@ -81,7 +84,9 @@ static_assert((Pitch<32>::TW - 32) * Pitch<32>::TW + 32 * (Pitch<32>::TW - 32) =
 // item = its index in block order).
 template <int T, int MODE>
 __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, int nunits,
-                                               const Item* __restrict__ items, const uint8_t* __restrict__ mask,
+                                               const Item* __restrict__ items,
+                                               const uint32_t* __restrict__ item_pairs,
+                                               const uint8_t* __restrict__ mask,
                                                const uint2* __restrict__ coord, const float2* __restrict__ grid, int K,
                                                int tpa, KBPoly P, float2* __restrict__ out,
                                                const float2* __restrict__ y, const float2* __restrict__ v,
@@ -89,6 +94,7 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int NV = MAX_BIN / GT;
   constexpr int NWV = GT / 64;
+  static_assert(GT == GRID_LANES && NV == 4, "the item order's slot pairs (item_order)");
   __shared__ float2 tile[TW * TP];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
@@ -121,38 +127,79 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
         }
       }
       double sr = 0.0, se = 0.0;
-#pragma unroll
-      for (int k = 0; k < NV; ++k) {
+      auto emit = [&](int k, float2 acc) {
         const int s = threadIdx.x + k * GT;
-        if (s < it.w) {
-          float wx[KB_J], wy[KB_J];
-          int cx, cy;
-          kb_weights(c[k].x, P, wx, cx);
-          kb_weights(c[k].y, P, wy, cy);
-          const float2* base = &tile[(cy - ty * T) * TP + (cx - tx * T)];
-          float2 acc = make_float2(0.f, 0.f);
+        if (MODE == DG_APPLY) {
+          out[it.z + s] = acc;
+        } else {
+          const float2 e = make_float2(acc.x - yy[k].x, acc.y - yy[k].y);
+          const float2 r = make_float2(vv[k].x + e.x, vv[k].y + e.y);
+          if (MODE == DG_RESIDUAL) out[it.z + s] = r;
+          sr += double(r.x) * r.x + double(r.y) * r.y;
+          se += double(e.x) * e.x + double(e.y) * e.y;
+        }
+      };
+      auto single = [&](int k) {
+        float wx[KB_J], wy[KB_J];
+        int cx, cy;
+        kb_weights(c[k].x, P, wx, cx);
+        kb_weights(c[k].y, P, wy, cy);
+        const float2* base = &tile[(cy - ty * T) * TP + (cx - tx * T)];
+        float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
-          for (int ra = 0; ra < KB_J; ++ra) {
-            const float2* row = base + ra * TP;
-            float2 rs = make_float2(0.f, 0.f);
+        for (int ra = 0; ra < KB_J; ++ra) {
+          const float2* row = base + ra * TP;
+          float2 rs = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int b = 0; b < KB_J; ++b) {
-              const float2 g = row[b];
-              rs.x = fmaf(wx[b], g.x, rs.x);
-              rs.y = fmaf(wx[b], g.y, rs.y);
-            }
-            acc.x = fmaf(wy[ra], rs.x, acc.x);
-            acc.y = fmaf(wy[ra], rs.y, acc.y);
+          for (int b = 0; b < KB_J; ++b) {
+            const float2 g = row[b];
+            rs.x = fmaf(wx[b], g.x, rs.x);
+            rs.y = fmaf(wx[b], g.y, rs.y);
           }
-          if (MODE == DG_APPLY) {
-            out[it.z + s] = acc;
-          } else {
-            const float2 e = make_float2(acc.x - yy[k].x, acc.y - yy[k].y);
-            const float2 r = make_float2(vv[k].x + e.x, vv[k].y + e.y);
-            if (MODE == DG_RESIDUAL) out[it.z + s] = r;
-            sr += double(r.x) * r.x + double(r.y) * r.y;
-            se += double(e.x) * e.x + double(e.y) * e.y;
+          acc.x = fmaf(wy[ra], rs.x, acc.x);
+          acc.y = fmaf(wy[ra], rs.y, acc.y);
+        }
+        emit(k, acc);
+      };
+      // two visibilities of one cell: each staged value is read once for both
+      auto pair = [&](int k, int k2) {
+        float wx[KB_J], wy[KB_J], wx2[KB_J], wy2[KB_J];
+        int cx, cy, cx2, cy2;
+        kb_weights(c[k].x, P, wx, cx);
+        kb_weights(c[k].y, P, wy, cy);
+        kb_weights(c[k2].x, P, wx2, cx2);
+        kb_weights(c[k2].y, P, wy2, cy2);
+        const float2* base = &tile[(cy - ty * T) * TP + (cx - tx * T)];
+        float2 acc = make_float2(0.f, 0.f), acc2 = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int ra = 0; ra < KB_J; ++ra) {
+          const float2* row = base + ra * TP;
+          float2 rs = make_float2(0.f, 0.f), rs2 = make_float2(0.f, 0.f);
+#pragma unroll
+          for (int b = 0; b < KB_J; ++b) {
+            const float2 g = row[b];
+            rs.x = fmaf(wx[b], g.x, rs.x);
+            rs.y = fmaf(wx[b], g.y, rs.y);
+            rs2.x = fmaf(wx2[b], g.x, rs2.x);
+            rs2.y = fmaf(wx2[b], g.y, rs2.y);
           }
+          acc.x = fmaf(wy[ra], rs.x, acc.x);
+          acc.y = fmaf(wy[ra], rs.y, acc.y);
+          acc2.x = fmaf(wy2[ra], rs2.x, acc2.x);
+          acc2.y = fmaf(wy2[ra], rs2.y, acc2.y);
+        }
+        emit(k, acc);
+        emit(k2, acc2);
+      };
+      const uint32_t npair = item_pairs[it.y];
+#pragma unroll
+      for (int j = 0; j < NV / 2; ++j) {
+        const int k = 2 * j, s = threadIdx.x + k * GT;
+        if (threadIdx.x < int((npair >> (16 * j)) & 0xffffu)) {
+          pair(k, k + 1);
+        } else {
+          if (s < it.w) single(k);
+          if (s + GT < it.w) single(k + 1);
         }
       }
       if (MODE != DG_APPLY) {
@@ -239,11 +286,13 @@ constexpr unsigned long long ROUND_BIAS_BITS = 0x4B4000004B400000ull;
 // (LDS integer atomics are an order of magnitude faster than LDS float atomics on this
 // hardware), Re in the low and Im in the high 32 bits of one word: every value is scaled
 // by a power of two 2^E such that the item's sum of |Re| + |Im|, which bounds any cell's
-// sum (the kernel weights are at most 1), stays below 2^30, and each single contribution
-// below 2^22 in magnitude.  A contribution t = w x is rounded to an integer n by one FMA
+// sum (the kernel weights are at most 1), stays below 2^30, and the sum of the two
+// contributions of a thread's slot pair (one rounded word for a same-cell pair) below 2^22
+// in magnitude.  A contribution t = w x is rounded to an integer n by one FMA
 // that adds B = 1.5 * 2^23: for |t| < 2^22 the result lies in [2^23, 2^24), where floats are
 // the integers, so it is B + n with n = t rounded to nearest (ties to even), and its bit
-// pattern is 0x4B400000 + n.  The word is then (bits of Im) 2^32 + (bits of Re) minus the
+// pattern is 0x4B400000 + n.  A same-cell pair adds its second contribution with a second
+// FMA onto B + n_2, which is again an integer in that range, so it yields B + n_2 + n_1.  The word is then (bits of Im) 2^32 + (bits of Re) minus the
 // constant 0x4B4000004B400000, which equals n_re + n_im 2^32 in two's complement (a
 // negative n_re borrows from the high half); decoding subtracts the sign-extended low field.
 // Rounding is at most 2^-E-1 per contribution.
@@ -269,6 +318,7 @@ template <int T, int MODE>
 __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(const int4* __restrict__ units, int nunits,
                                                    const Item* __restrict__ items,
                                                    const uint32_t* __restrict__ item_box,
+                                                   const uint32_t* __restrict__ item_pairs,
                                                    const uint8_t* __restrict__ mask, const uint2* __restrict__ coord,
                                                    float2* __restrict__ grid, float2* __restrict__ halo, int K,
                                                    int tpa, KBPoly P, const float2* __restrict__ y,
@@ -281,6 +331,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   constexpr int NV = MAX_BIN / GGT;
   constexpr int NWV = GGT / 64;
   constexpr int NC = (TW * TW + GGT - 1) / GGT;  // region cells per thread
+  static_assert(NV == 4, "two slot pairs per thread (item_order)");
   __shared__ unsigned long long acci[2][TW * TP];
   __shared__ float red_b[2][NWV], red_m[2][NWV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -332,9 +383,15 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
         }
         crd[k] = rc[k];
         babs += fabsf(val[k].x) + fabsf(val[k].y);
-        bmax = fmaxf(bmax, fmaxf(fabsf(val[k].x), fabsf(val[k].y)));
+      } else {
+        val[k] = make_float2(0.f, 0.f);
       }
     }
+    // the largest sum of one component over a slot pair (a same-cell pair adds both
+    // contributions into one rounded word; for two singles this bounds each as well)
+#pragma unroll
+    for (int k = 0; k < NV; k += 2)
+      bmax = fmaxf(bmax, fmaxf(fabsf(val[k].x) + fabsf(val[k + 1].x), fabsf(val[k].y) + fabsf(val[k + 1].y)));
     babs = wave_sum(babs);
     bmax = wave_max(bmax);
     if (lane == 0) {
@@ -405,8 +462,9 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
         itn = items[qn];
         load_raw(itn);
       }
-      // 2^E with bound * 2^E < 2^30 and bmax * 2^E < 2^22 / 1.001 (the factors guard the
-      // bounds' own rounding, the kernel fit's excess over 1 and the rounding of w x)
+      // 2^E with bound * 2^E < 2^30 and bmax * 2^E < 2^22 / 1.001, so that a pair's two
+      // rounded contributions sum to less than 2^22 (the factors guard the bounds' own
+      // rounding, the kernel fit's excess over 1 and the rounding of w x)
       int ex = 0, exm = 0;
       if (bound > 0.f) {
         frexpf(bound * 1.0001f, &ex);
@@ -415,26 +473,58 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
       const int e2 = min(30 - ex, 22 - exm);
       const float scale = ldexpf(1.f, e2), inv = ldexpf(1.f, -e2);
       if (bound > 0.f) {
+        const uint32_t npair = item_pairs[it.y];
+        // one visibility: per tap an FMA per component and one atomic
+        auto single = [&](int k) {
+          const float vr = val[k].x * scale, vi = val[k].y * scale;
+          float wx[KB_J], wy[KB_J];
+          int cx, cy;
+          kb_weights(crd[k].x, P, wx, cx);
+          kb_weights(crd[k].y, P, wy, cy);
+          unsigned long long* base = &acci[buf][(cy - ty * T) * TP + (cx - tx * T)];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-          const int s = threadIdx.x + k * GGT;
-          if (s < it.w) {
-            const float vr = val[k].x * scale, vi = val[k].y * scale;
-            float wx[KB_J], wy[KB_J];
-            int cx, cy;
-            kb_weights(crd[k].x, P, wx, cx);
-            kb_weights(crd[k].y, P, wy, cy);
-            unsigned long long* base = &acci[buf][(cy - ty * T) * TP + (cx - tx * T)];
+          for (int r = 0; r < KB_J; ++r) {
+            const float tr = wy[r] * vr, ti = wy[r] * vi;
 #pragma unroll
-            for (int r = 0; r < KB_J; ++r) {
-              const float tr = wy[r] * vr, ti = wy[r] * vi;
-#pragma unroll
-              for (int b = 0; b < KB_J; ++b) {
-                const unsigned lo = __float_as_uint(fmaf(wx[b], tr, ROUND_BIAS));
-                const unsigned hi = __float_as_uint(fmaf(wx[b], ti, ROUND_BIAS));
-                atomicAdd(base + r * TP + b, ((static_cast<unsigned long long>(hi) << 32) | lo) - ROUND_BIAS_BITS);
-              }
+            for (int b = 0; b < KB_J; ++b) {
+              const unsigned lo = __float_as_uint(fmaf(wx[b], tr, ROUND_BIAS));
+              const unsigned hi = __float_as_uint(fmaf(wx[b], ti, ROUND_BIAS));
+              atomicAdd(base + r * TP + b, ((static_cast<unsigned long long>(hi) << 32) | lo) - ROUND_BIAS_BITS);
             }
+          }
+        };
+        // two visibilities of one cell (the plan guarantees it): each contribution is
+        // rounded by its own FMA (the inner one leaves an integer-valued float, so the outer
+        // one adds the second rounded value exactly) and the pair takes one atomic per tap
+        auto pair = [&](int k, int k2) {
+          const float vr = val[k].x * scale, vi = val[k].y * scale;
+          const float vr2 = val[k2].x * scale, vi2 = val[k2].y * scale;
+          float wx[KB_J], wy[KB_J], wx2[KB_J], wy2[KB_J];
+          int cx, cy, cx2, cy2;
+          kb_weights(crd[k].x, P, wx, cx);
+          kb_weights(crd[k].y, P, wy, cy);
+          kb_weights(crd[k2].x, P, wx2, cx2);
+          kb_weights(crd[k2].y, P, wy2, cy2);
+          unsigned long long* base = &acci[buf][(cy - ty * T) * TP + (cx - tx * T)];
+#pragma unroll
+          for (int r = 0; r < KB_J; ++r) {
+            const float tr = wy[r] * vr, ti = wy[r] * vi, tr2 = wy2[r] * vr2, ti2 = wy2[r] * vi2;
+#pragma unroll
+            for (int b = 0; b < KB_J; ++b) {
+              const unsigned lo = __float_as_uint(fmaf(wx[b], tr, fmaf(wx2[b], tr2, ROUND_BIAS)));
+              const unsigned hi = __float_as_uint(fmaf(wx[b], ti, fmaf(wx2[b], ti2, ROUND_BIAS)));
+              atomicAdd(base + r * TP + b, ((static_cast<unsigned long long>(hi) << 32) | lo) - ROUND_BIAS_BITS);
+            }
+          }
+        };
+#pragma unroll
+        for (int j = 0; j < NV / 2; ++j) {
+          const int k = 2 * j, s = threadIdx.x + k * GGT;
+          if (threadIdx.x < int((npair >> (16 * j)) & 0xffffu)) {
+            pair(k, k + 1);
+          } else {
+            if (s < it.w) single(k);
+            if (s + GGT < it.w) single(k + 1);
           }
         }
       }
@@ -623,7 +713,7 @@ int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const
   }
   if (nunits > 0) {
     hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GGT), 0, s, units, nunits, items,
-                       p.item_box, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, shrink,
+                       p.item_box, p.item_pairs, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, shrink,
                        sliced ? p.unit_patch : nullptr, p.spatch, fresh ? 1 : 0, sliced ? 0 : 1);
     RI_LAUNCH_CHECK();
   }
@@ -686,7 +776,7 @@ int degrid_batched_t(const Plan& p, const float2* grid, float2* out, const float
                      double* part, const uint8_t* mask, hipStream_t s) {
   if (p.n_dunits > 0) {
     hipLaunchKernelGGL((k_degrid<T, MODE>), dim3(wgs_for(p, p.n_dunits)), dim3(GT), 0, s, p.dunits, p.n_dunits,
-                       p.titems, mask, p.coord, grid, p.K, p.tpa, p.poly, out, y, v, part);
+                       p.titems, p.item_pairs, mask, p.coord, grid, p.K, p.tpa, p.poly, out, y, v, part);
     RI_LAUNCH_CHECK();
   }
   return RI_OK;
@@ -726,8 +816,8 @@ int degrid_residual_block(const Plan& p, int block, const float2* grid, const fl
   const int a = p.bunit_off_host[block], b = p.bunit_off_host[block + 1];
   if (p.dde.on()) return dde_degrid(p, p.bunits + a, b - a, p.items, nullptr, grid, e, y, v, p.item_part, s);
   const dim3 grid_dim(wgs_for(p, b - a));
-#define ARGS p.bunits + a, b - a, p.items, (const uint8_t*)nullptr, p.coord, grid, p.K, p.tpa, p.poly, e, \
-             y, v, p.item_part
+#define ARGS p.bunits + a, b - a, p.items, p.item_pairs, (const uint8_t*)nullptr, p.coord, grid, p.K, p.tpa, \
+             p.poly, e, y, v, p.item_part
   RI_TILE_DISPATCH(k_degrid, DG_RESIDUAL)
 #undef ARGS
   RI_LAUNCH_CHECK();

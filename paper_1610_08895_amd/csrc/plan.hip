@@ -55,6 +55,7 @@ void destroy_plan(Plan& p) {
   dev_free(p.order);
   dev_free(p.items);
   dev_free(p.item_box);
+  dev_free(p.item_pairs);
   dev_free(p.item_off);
   dev_free(p.block_off);
   dev_free(p.twiddle);
@@ -78,23 +79,70 @@ void destroy_plan(Plan& p) {
   dde_destroy(p.dde);
 }
 
-// Reorders the visibilities of one work item (sorted by tile-local cell, key low word =
-// ly * T + lx) so that every 64 consecutive ones, which one wavefront processes together,
-// spread their staged-tile addresses ly * (T + 9) + lx evenly over the LDS banks: the
-// visibilities are dealt round-robin from one queue per bank (32 banks of 8-byte words).
-void lds_bank_order(std::pair<uint64_t, int64_t>* kv, int64_t w, int T) {
+using KV = std::pair<uint64_t, int64_t>;  // (tile << 32 | tile-local cell ly * T + lx, index)
+
+// Reorders a list of visibilities (or of same-cell pairs, by their first member) so that
+// every 64 consecutive ones, which one wavefront processes together, spread their
+// staged-tile addresses ly * (T + 9) + lx evenly over the LDS banks: they are dealt
+// round-robin from one queue per bank (32 banks of 8-byte words).
+template <class E, class Key>
+void lds_bank_order(std::vector<E>& v, int T, Key key) {
   constexpr int NB = 32;
-  std::vector<std::pair<uint64_t, int64_t>> q[NB];
-  for (int64_t k = 0; k < w; ++k) {
-    const uint32_t local = uint32_t(kv[k].first);
+  std::vector<E> q[NB];
+  for (const E& e : v) {
+    const uint32_t local = uint32_t(key(e));
     const uint32_t ly = local / T, lx = local % T;
-    q[(ly * uint32_t(T + 9) + lx) % NB].push_back(kv[k]);
+    q[(ly * uint32_t(T + 9) + lx) % NB].push_back(e);
   }
-  size_t head[NB] = {};
-  int64_t out = 0;
-  while (out < w)
+  size_t head[NB] = {}, out = 0;
+  while (out < v.size())
     for (int b = 0; b < NB; ++b)
-      if (head[b] < q[b].size()) kv[out++] = q[b][head[b]++];
+      if (head[b] < q[b].size()) v[out++] = q[b][head[b]++];
+}
+
+// Orders the w visibilities of one work item (sorted by tile-local cell) for the kernels.
+// Thread t of a gridding workgroup takes positions t + k GRID_LANES, k = 0 .. MAX_BIN /
+// GRID_LANES - 1, and treats slots 2j and 2j + 1 as a pair when t < P_j: two visibilities
+// of the same cell whose 64 taps it adds with one atomic each.  Same-cell visibilities are
+// paired greedily, and the pairs are placed at positions (t + 2j L, t + (2j + 1) L), t < P_j,
+// where L = GRID_LANES and P_j is as many whole wavefronts (64) of pairs as fit; the rest
+// (odd members and pairs that do not fit) fill the other positions as singles.  Pairs and singles are each dealt over the LDS
+// banks.  Returns P_0 | P_1 << 16.
+uint32_t item_order(KV* kv, int64_t w, int T) {
+  constexpr int L = GRID_LANES;
+  static_assert(MAX_BIN == 4 * L, "two slot pairs per thread");
+  std::vector<std::pair<KV, KV>> pairs;
+  std::vector<KV> singles;
+  for (int64_t k = 0; k < w;) {
+    int64_t e = k;
+    while (e < w && uint32_t(kv[e].first) == uint32_t(kv[k].first)) ++e;
+    for (; k + 1 < e; k += 2) pairs.push_back({kv[k], kv[k + 1]});
+    if (k < e) singles.push_back(kv[k++]);
+  }
+  const int64_t cap0 = std::clamp<int64_t>(w - L, 0, L), cap1 = std::clamp<int64_t>(w - 3 * L, 0, L);
+  // whole wavefronts of pairs, so that no wavefront runs both the pair and the single path
+  const int64_t p0 = std::min<int64_t>(int64_t(pairs.size()), cap0) / 64 * 64;
+  const int64_t p1 = std::min<int64_t>(int64_t(pairs.size()) - p0, cap1) / 64 * 64;
+  for (size_t j = size_t(p0 + p1); j < pairs.size(); ++j) {
+    singles.push_back(pairs[j].first);
+    singles.push_back(pairs[j].second);
+  }
+  pairs.resize(size_t(p0 + p1));
+  lds_bank_order(pairs, T, [](const std::pair<KV, KV>& e) { return e.first.first; });
+  lds_bank_order(singles, T, [](const KV& e) { return e.first; });
+  std::vector<KV> out(w);
+  std::vector<char> used(w, 0);
+  for (int64_t j = 0; j < p0 + p1; ++j) {
+    const int64_t a = j < p0 ? j : 2 * L + (j - p0);
+    out[a] = pairs[j].first;
+    out[a + L] = pairs[j].second;
+    used[a] = used[a + L] = 1;
+  }
+  size_t next = 0;
+  for (int64_t a = 0; a < w; ++a)
+    if (!used[a]) out[a] = singles[next++];
+  std::copy(out.begin(), out.end(), kv);
+  return uint32_t(p0) | uint32_t(p1) << 16;
 }
 
 int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t* off, int J, double beta,
@@ -145,10 +193,11 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   const double to_cells = double(K) / (2.0 * M_PI);
   p.order_host.resize(M);
   std::vector<std::vector<Item>> block_items(d);
+  std::vector<std::vector<uint32_t>> block_pairs(d);
   const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   auto work = [&](int i) {
     const int64_t lo = off[i], hi = off[i + 1];
-    std::vector<std::pair<uint64_t, int64_t>> kv(hi - lo);
+    std::vector<KV> kv(hi - lo);
     for (int64_t m = lo; m < hi; ++m) {
       const uint32_t cx = pack_coord(double(uv[2 * m]) * to_cells, K);
       const uint32_t cy = pack_coord(double(uv[2 * m + 1]) * to_cells, K);
@@ -160,6 +209,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
     }
     std::sort(kv.begin(), kv.end());
     auto& its = block_items[i];
+    auto& prs = block_pairs[i];
     int64_t k = 0;
     while (k < hi - lo) {
       const uint64_t tile = kv[k].first >> 32;
@@ -167,7 +217,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
       while (e < hi - lo && (kv[e].first >> 32) == tile) ++e;
       for (int64_t a = k; a < e; a += p.bin) {
         const int64_t w = std::min<int64_t>(p.bin, e - a);
-        lds_bank_order(kv.data() + a, w, T);
+        prs.push_back(item_order(kv.data() + a, w, T));
         its.push_back(make_int4(i, int(tile), int(lo + a), int(w)));
       }
       k = e;
@@ -186,10 +236,12 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   std::vector<uint2> coord_sorted(M);
   for (int64_t k = 0; k < M; ++k) coord_sorted[k] = packed[p.order_host[k]];
   std::vector<Item> items;
+  std::vector<uint32_t> item_pairs;
   p.item_off_host.assign(d + 1, 0);
   for (int i = 0; i < d; ++i) {
     p.item_off_host[i] = int(items.size());
     items.insert(items.end(), block_items[i].begin(), block_items[i].end());
+    item_pairs.insert(item_pairs.end(), block_pairs[i].begin(), block_pairs[i].end());
   }
   p.item_off_host[d] = int(items.size());
   p.n_items = int(items.size());
@@ -350,6 +402,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_TRY(dev_alloc(&p.order, M));
   RI_TRY(dev_alloc(&p.items, items.size()));
   RI_TRY(dev_alloc(&p.item_box, items.size()));
+  RI_TRY(dev_alloc(&p.item_pairs, items.size()));
   RI_TRY(dev_alloc(&p.item_off, d + 1));
   RI_TRY(dev_alloc(&p.block_off, d + 1));
   RI_TRY(dev_alloc(&p.twiddle, K));
@@ -381,6 +434,7 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   RI_HIP(hipMemcpyAsync(p.items, items_dev.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.titems, titems.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.item_box, item_box.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  RI_HIP(hipMemcpyAsync(p.item_pairs, item_pairs.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.item_off, p.item_off_host.data(), (d + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.block_off, p.block_off_host.data(), (d + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.twiddle, tw.data(), K * sizeof(float2), hipMemcpyHostToDevice, s));

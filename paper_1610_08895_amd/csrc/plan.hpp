@@ -48,7 +48,8 @@ __device__ __forceinline__ void kb_weights(unsigned packed, const KBPoly& P, flo
 // The device copies carry in y the item's index in block order instead (which indexes the
 // per-item arrays); the tile comes from the unit that lists the item.
 using Item = int4;
-constexpr int MAX_BIN = 1024;    // largest `bin` (the gridding kernel stages an item's values in LDS)
+constexpr int MAX_BIN = 1024;    // largest `bin` (4 visibilities per thread of a gridding workgroup)
+constexpr int GRID_LANES = 256;  // threads per workgroup of the tile gridding
 constexpr int DUNIT_VIS = 2048;  // visibilities per degridding unit (several items of one tile)
 constexpr int PART_WAVES = 4;    // FP64 norm partials per work item (one per wavefront)
 // Cells of a tile's halo ring: its (tile + 8)^2 region (the tile and the kernel's reach)
@@ -101,6 +102,9 @@ struct Plan {
   // taps relative to its tile origin, one byte each (row min, row max, column min, column
   // max from the low byte up)
   uint32_t* item_box = nullptr;
+  // n_items: P_0 | P_1 << 16, the threads of a gridding workgroup that hold a same-cell pair
+  // in slots (0, 1) and (2, 3) of the item (see item_order)
+  uint32_t* item_pairs = nullptr;
   int* item_off = nullptr;    // d + 1
   int64_t* block_off = nullptr;  // d + 1 block offsets (visibilities, plan order = user order per block)
   float2* twiddle = nullptr;  // K forward twiddles exp(-2 pi i k / K)

@@ -102,6 +102,19 @@ def _gpu_grad(R, plan, yp, eps, prm, masks, x, checkpoint):
     return float(snr.detach()), params.grad.numpy().copy()
 
 
+# The FP32 noise of the unrolled forward and reverse sweeps reaches both components of
+# (dSNR/dtau, dSNR/dsigma) with about the same absolute size, so the error is bounded
+# relative to the gradient's norm: observed at most 6e-6 of it (2.4e-5 absolute in a
+# dSNR/dsigma of 0.09, next to a dSNR/dtau of 4.1).
+GRAD_TOL = 3e-5
+
+
+def _check_grad(g, ref):
+    ref = np.asarray(ref, dtype=np.float64)
+    err = np.abs(np.asarray(g, dtype=np.float64) - ref)
+    assert np.all(err <= GRAD_TOL * np.linalg.norm(ref)), (g, ref, err / np.linalg.norm(ref))
+
+
 @pytest.mark.parametrize("checkpoint", [5, 1, 10])
 def test_unrolled_gradient_matches_oracle(R, checkpoint):
     """10 iterations with fixed random masks (p = 0.7), segments of 5, 1 and 10."""
@@ -110,8 +123,7 @@ def test_unrolled_gradient_matches_oracle(R, checkpoint):
     s_gpu, g = _gpu_grad(R, plan, yp, eps, prm, masks, x, checkpoint)
     print(f"SNR {s_gpu:.6f} / {s_ref:.6f}; dtau {g[0]:.7g} / {dtau:.7g}; dsigma {g[1]:.7g} / {dsig:.7g}")
     assert s_gpu == pytest.approx(s_ref, abs=1e-3)
-    assert g[0] == pytest.approx(dtau, rel=1e-4)
-    assert g[1] == pytest.approx(dsig, rel=1e-4)
+    _check_grad(g, [dtau, dsig])
 
 
 def test_unrolled_gradient_reference_512(R):
@@ -135,5 +147,4 @@ def test_unrolled_gradient_reference_512(R):
     print(f"SNR {s_gpu:.6f} / {ref['snr']:.6f}; dtau {g[0]:.7g} / {ref['dsnr_dtau']:.7g}; "
           f"dsigma {g[1]:.7g} / {ref['dsnr_dsigma']:.7g}")
     assert s_gpu == pytest.approx(ref["snr"], abs=1e-3)
-    assert g[0] == pytest.approx(ref["dsnr_dtau"], rel=1e-4)
-    assert g[1] == pytest.approx(ref["dsnr_dsigma"], rel=1e-4)
+    _check_grad(g, [ref["dsnr_dtau"], ref["dsnr_dsigma"]])

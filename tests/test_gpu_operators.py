@@ -290,3 +290,33 @@ def test_light_units_match_oracle(R, tile):
     mask = np.array([1, 0, 1, 1, 0, 1], np.uint8)
     xm = plan.phi_adj(wt, mask=torch.tensor(mask, device="cuda")).cpu().numpy()
     assert rel_l2(xm, meas.phi_adj_real(w, blocks=np.flatnonzero(mask))) < TOL
+
+
+@pytest.mark.parametrize("bin", [1024, 600, 320, 64])
+def test_same_cell_pairs_match_oracle(R, bin):
+    """Visibilities crowded one to eight to a cell over a few tiles, so that the plan pairs
+    same-cell visibilities in whole wavefronts (items of up to `bin`: both slot pairs, one,
+    or none when an item is too small), with odd counts left single and ragged blocks;
+    Phi, Phi^dagger and masked Phi^dagger against the oracle."""
+    n = 64
+    K = 2 * n
+    rng = np.random.default_rng(77 + bin)
+    cells = rng.integers(0, 40, (700, 2))
+    counts = rng.integers(1, 9, 700)
+    kap = np.repeat(cells, counts, axis=0) + rng.uniform(0.0, 1.0, (int(counts.sum()), 2))
+    uv = 2 * np.pi * kap / K
+    uv = np.where(uv >= np.pi, uv - 2 * np.pi, uv).astype(np.float32)
+    M = uv.shape[0]
+    off = np.array([0, 1, 900, 2100, M])  # blocks hold runs of whole cells, and one visibility
+    x = synth.sky(n, 5, 10, rng)
+    plan = R.Plan(n, uv, off, bin=bin)
+    order = plan.order()
+    meas = Measurement(uv, off, (n, n))
+    y = to_user(plan.phi(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy(), order)
+    assert rel_l2(y, meas.phi(x)) < TOL
+    w = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    wt = torch.tensor(to_plan(w, order), dtype=torch.complex64, device="cuda")
+    assert rel_l2(plan.phi_adj(wt).cpu().numpy(), meas.phi_adj_real(w)) < TOL
+    mask = np.array([1, 0, 1, 1], np.uint8)
+    xm = plan.phi_adj(wt, mask=torch.tensor(mask, device="cuda")).cpu().numpy()
+    assert rel_l2(xm, meas.phi_adj_real(w, blocks=np.flatnonzero(mask))) < TOL
