@@ -262,16 +262,12 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
   // fork: the sparsity branch needs only x~ of the previous iteration.  It starts after the
   // forward FFT so that it shares the GPU with the gather / scatter kernels rather than with
   // the column FFT pass, which needs most of a CU's LDS per workgroup (measured faster).
-  // Timed runs keep it on the calling stream so that each stage is measured alone.
+  // Timed runs keep it on the calling stream so that each stage is measured alone.  The
+  // data branch is enqueued (and, under capture, recorded) before the sparsity branch: a
+  // replayed graph then keeps it on the queue of the forward FFT, so neither the fork nor
+  // the join (the sparsity branch ends first) puts a wait between two queues on its path.
   const bool fork = !(P->timing && !ri::capturing(stream));
-  if (fork) {
-    RI_HIP(hipEventRecord(P->ev_fork, stream));
-    RI_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
-    RI_TRY(ri::sparsity_branch(P, P->side));
-    RI_HIP(hipEventRecord(P->ev_join, P->side));
-  } else {
-    RI_TRY(ri::sparsity_branch(P, stream));
-  }
+  if (fork) RI_HIP(hipEventRecord(P->ev_fork, stream));
   RI_STAGE(P, RI_STAGE_DEGRID, stream,
            ri::degrid_residual(p, p.grid, P->y, P->v, P->e, mask, stream));
   RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, mask, P->stats, stats, stream, P->eps, P->shrink));
@@ -283,8 +279,15 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
     RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project(p, P->e, P->v, P->shrink, mask, P->sum, stream));
   RI_STAGE(P, RI_STAGE_GRID_HALO, stream, ri::grid_halo(p, P->sum, stream));
   RI_STAGE(P, RI_STAGE_IFFT_COLS, stream, ri::fft_adjoint_cols(p, P->sum, stream));
-  // join, then the adjoint row pass with steps 17-18 fused into its output
-  if (fork) RI_HIP(hipStreamWaitEvent(stream, P->ev_join, 0));
+  if (fork) {
+    RI_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+    RI_TRY(ri::sparsity_branch(P, P->side));
+    RI_HIP(hipEventRecord(P->ev_join, P->side));
+    // join, then the adjoint row pass with steps 17-18 fused into its output
+    RI_HIP(hipStreamWaitEvent(stream, P->ev_join, 0));
+  } else {
+    RI_TRY(ri::sparsity_branch(P, stream));
+  }
   const ri::PrimalUpdate upd{P->st, P->x, P->xt, float(P->prm.tau), float(P->prm.sigma), float(P->prm.varsigma)};
   RI_STAGE(P, RI_STAGE_IFFT_ROWS, stream, ri::fft_adjoint_rows_update(p, upd, stream));
   P->iter += 1;
