@@ -87,6 +87,8 @@ __global__ __launch_bounds__(NT) void k_adj_cols(const float2* __restrict__ grid
   __shared__ float2 twl[TwLds<K, W>::size];
   const int c0 = panel_of(blockIdx.x, gridDim.x) * W;
   auto load = [&](int w, int k) -> float2 { return grid[size_t(k) * K + c0 + w]; };
+  // the data branch's kernels issue ahead of the sparsity branch's waves sharing their SIMDs
+  __builtin_amdgcn_s_setprio(3);
   auto store = [&](int w, int q, float2 v) {
     const int r = pix_of(q, n, K);
     if (r >= 0) rows[size_t(r) * K + c0 + w] = v;

@@ -95,6 +95,8 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
   constexpr int NV = MAX_BIN / GT;
   constexpr int NWV = GT / 64;
   static_assert(GT == GRID_LANES && NV == 4, "the item order's slot pairs (item_order)");
+  // the data branch's kernels issue ahead of the sparsity branch's waves sharing their SIMDs
+  __builtin_amdgcn_s_setprio(3);
   __shared__ float2 tile[TW * TP];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
@@ -223,6 +225,8 @@ __global__ __launch_bounds__(GT) void k_block_stats(const uint8_t* __restrict__ 
                                                     float* __restrict__ shrink) {
   __shared__ double red[2][GT / 64];
   const int i = blockIdx.x;
+  // the data branch's kernels issue ahead of the sparsity branch's waves sharing their SIMDs
+  __builtin_amdgcn_s_setprio(3);
   if (mask != nullptr && mask[i] == 0) {
     if (out != nullptr && threadIdx.x == 0) {  // quiet NaN, stored as its bit pattern
       unsigned long long* o = reinterpret_cast<unsigned long long*>(out);
@@ -332,6 +336,8 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   constexpr int NWV = GGT / 64;
   constexpr int NC = (TW * TW + GGT - 1) / GGT;  // region cells per thread
   static_assert(NV == 4, "two slot pairs per thread (item_order)");
+  // the data branch's kernels issue ahead of the sparsity branch's waves sharing their SIMDs
+  __builtin_amdgcn_s_setprio(3);
   __shared__ unsigned long long acci[2][TW * TP];
   __shared__ float red_b[2][NWV], red_m[2][NWV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -590,6 +596,8 @@ __global__ __launch_bounds__(GT) void k_grid_halo(const float2* __restrict__ hal
   constexpr int TW = T + 8;
   constexpr int R0 = KB_J / 2 - 1;
   constexpr int NEAR = KB_J / 2, FAR = R0;  // edge rows / columns reached from outside
+  // the data branch's kernels issue ahead of the sparsity branch's waves sharing their SIMDs
+  __builtin_amdgcn_s_setprio(3);
   constexpr int NE = T * T - (T - NEAR - FAR) * (T - NEAR - FAR);  // edge cells
   const int t = blockIdx.x;
   const int ty = t / tpa, tx = t - (t / tpa) * tpa;
