@@ -1,11 +1,11 @@
 // Measurement-operator plan and the Phi / Phi^dagger entry points (Eq. 3, Eq. 8).
 //
-// Plan creation, on the host in FP64:
+// Plan creation:
 //   * each u-v coordinate becomes kappa = u K / (2 pi) wrapped to [0, K), stored as a
 //     12-bit cell plus a 20-bit fraction (position error <= 2^-21 cell, i.e. < 1e-6 rad of
-//     phase at the image edge);
-//   * inside each block, visibilities are sorted by (grid tile, cell) and cut into work
-//     items of at most `bin` visibilities of one tile;
+//     phase at the image edge), in FP64 on the device (plan_sort.hip);
+//   * the visibilities are sorted by (block, grid tile, cell) on the device, and inside each
+//     block cut on the host into work items of at most `bin` visibilities of one tile;
 //   * Kaiser-Bessel weights are fitted per tap by degree-7 polynomials (Chebyshev
 //     interpolation of the kernel evaluated with an I0 power series);
 //   * twiddles exp(-2 pi i k / K) and the pre-compensation S = 1/phi_hat(l/K) are
@@ -35,19 +35,6 @@ __global__ void k_permute(const float2* __restrict__ src, float2* __restrict__ d
 __global__ void k_copy_f32(const float* __restrict__ a, float* __restrict__ b, size_t n) {
   for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
     b[i] = a[i];
-}
-
-uint32_t pack_coord(double kappa, int K) {
-  double w = kappa - K * std::floor(kappa / K);  // [0, K]
-  long long cell = (long long)std::floor(w);
-  long long f = std::llround((w - double(cell)) * double(1u << FRAC_BITS));
-  if (f >= (1LL << FRAC_BITS)) {
-    f = 0;
-    cell += 1;
-  }
-  cell %= K;
-  if (cell < 0) cell += K;
-  return (uint32_t(cell) << FRAC_BITS) | uint32_t(f);
 }
 
 void destroy_plan(Plan& p) {
@@ -186,30 +173,33 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
       p.poly.o[j][k] = float(mono[size_t(j) * (2 * KB_HALF_DEG + 2) + 2 * k + 1]);
     }
 
-  // coordinates, sort and work items (blocks are independent: one host thread each)
+  // coordinates and the sort on the device (plan_sort), then the work items of each block
+  // on the host (blocks are independent: one host thread each)
   const int K = p.K, T = p.tile, tpa = p.tpa;
-  std::vector<uint2> packed(M);
-  std::vector<uint64_t> keys(M);
-  const double to_cells = double(K) / (2.0 * M_PI);
+  uint2* packed = nullptr;  // M packed coordinates, user order (device)
+  std::vector<uint64_t> skeys;
+  std::vector<int> sidx;
+  RI_TRY(plan_sort(uv, M, off, d, K, T, tpa, &packed, skeys, sidx, s));
+  struct Freer {
+    uint2*& q;
+    ~Freer() { dev_free(q); }
+  } free_packed{packed};
   p.order_host.resize(M);
   std::vector<std::vector<Item>> block_items(d);
-  std::vector<std::vector<uint32_t>> block_pairs(d);
+  std::vector<std::vector<uint32_t>> block_pairs(d), block_boxes(d);
+  std::atomic<int> bad{0};
   const unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   auto work = [&](int i) {
     const int64_t lo = off[i], hi = off[i + 1];
     std::vector<KV> kv(hi - lo);
-    for (int64_t m = lo; m < hi; ++m) {
-      const uint32_t cx = pack_coord(double(uv[2 * m]) * to_cells, K);
-      const uint32_t cy = pack_coord(double(uv[2 * m + 1]) * to_cells, K);
-      packed[m] = make_uint2(cx, cy);
-      const uint32_t gx = cx >> FRAC_BITS, gy = cy >> FRAC_BITS;
-      const uint64_t tile = uint64_t(gy / T) * tpa + gx / T;
-      const uint64_t local = uint64_t(gy % T) * T + gx % T;
-      kv[m - lo] = {(tile << 32) | local, m};
+    for (int64_t k = lo; k < hi; ++k) {
+      const uint64_t key = skeys[k];
+      if (int64_t(key >> 28) != i) bad = 1;  // the sort keeps the blocks where they are
+      kv[k - lo] = {(((key >> 12) & 0xFFFFu) << 32) | (key & 0xFFFu), int64_t(sidx[k])};
     }
-    std::sort(kv.begin(), kv.end());
     auto& its = block_items[i];
     auto& prs = block_pairs[i];
+    auto& bxs = block_boxes[i];
     int64_t k = 0;
     while (k < hi - lo) {
       const uint64_t tile = kv[k].first >> 32;
@@ -217,6 +207,16 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
       while (e < hi - lo && (kv[e].first >> 32) == tile) ++e;
       for (int64_t a = k; a < e; a += p.bin) {
         const int64_t w = std::min<int64_t>(p.bin, e - a);
+        // footprint box: the item's smallest and largest tile-local row and column
+        int b[4] = {T, -1, T, -1};
+        for (int64_t m = a; m < a + w; ++m) {
+          const int local = int(uint32_t(kv[m].first)), ly = local / T, lx = local % T;
+          b[0] = std::min(b[0], ly);
+          b[1] = std::max(b[1], ly);
+          b[2] = std::min(b[2], lx);
+          b[3] = std::max(b[3], lx);
+        }
+        bxs.push_back(uint32_t(b[0]) | uint32_t(b[1]) << 8 | uint32_t(b[2]) << 16 | uint32_t(b[3]) << 24);
         prs.push_back(item_order(kv.data() + a, w, T));
         its.push_back(make_int4(i, int(tile), int(lo + a), int(w)));
       }
@@ -233,32 +233,18 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
       });
     for (auto& t : th) t.join();
   }
-  std::vector<uint2> coord_sorted(M);
-  for (int64_t k = 0; k < M; ++k) coord_sorted[k] = packed[p.order_host[k]];
+  if (bad) return fail(RI_EHIP, "device sort returned visibilities outside their block");
   std::vector<Item> items;
-  std::vector<uint32_t> item_pairs;
+  std::vector<uint32_t> item_pairs, item_box;
   p.item_off_host.assign(d + 1, 0);
   for (int i = 0; i < d; ++i) {
     p.item_off_host[i] = int(items.size());
     items.insert(items.end(), block_items[i].begin(), block_items[i].end());
     item_pairs.insert(item_pairs.end(), block_pairs[i].begin(), block_pairs[i].end());
+    item_box.insert(item_box.end(), block_boxes[i].begin(), block_boxes[i].end());
   }
   p.item_off_host[d] = int(items.size());
   p.n_items = int(items.size());
-  std::vector<uint32_t> item_box(items.size());
-  for (size_t k = 0; k < items.size(); ++k) {
-    const Item& it = items[k];
-    const int oy = (it.y / tpa) * T, ox = (it.y % tpa) * T;
-    int b[4] = {T, -1, T, -1};
-    for (int64_t m = it.z; m < int64_t(it.z) + it.w; ++m) {
-      const int ly = int(coord_sorted[m].y >> FRAC_BITS) - oy, lx = int(coord_sorted[m].x >> FRAC_BITS) - ox;
-      b[0] = std::min(b[0], ly);
-      b[1] = std::max(b[1], ly);
-      b[2] = std::min(b[2], lx);
-      b[3] = std::max(b[3], lx);
-    }
-    item_box[k] = uint32_t(b[0]) | uint32_t(b[1]) << 8 | uint32_t(b[2]) << 16 | uint32_t(b[3]) << 24;
-  }
 
   // items grouped by tile, and tiles grouped into the four gridding colours
   p.n_tiles = tpa * tpa;
@@ -429,8 +415,8 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   }
   RI_TRY(dev_alloc(&p.norm_tmp, size_t(n) * n));
   RI_TRY(dev_alloc(&p.dsum, SUMSQ_SCRATCH));
-  RI_HIP(hipMemcpyAsync(p.coord, coord_sorted.data(), M * sizeof(uint2), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.order, p.order_host.data(), M * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  RI_TRY(plan_gather_coord(packed, p.order, M, p.coord, s));
   RI_HIP(hipMemcpyAsync(p.items, items_dev.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.titems, titems.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, s));
   RI_HIP(hipMemcpyAsync(p.item_box, item_box.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));

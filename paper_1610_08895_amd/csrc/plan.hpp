@@ -202,6 +202,16 @@ int grid_blocks_end(const Plan& p, float2* grid, hipStream_t s);
 // grid = G^dagger v over all items (rebuilds the running sum from scratch).
 int grid_all(const Plan& p, const float2* v, float2* grid, hipStream_t s);
 
+// ---- plan creation on the device (plan_sort.hip) ----
+// Packs the M coordinates (uv host, user order) into *packed (device, allocated here, the
+// caller frees it) and sorts the visibilities by (block, tile, cell in the tile), stably;
+// keys_sorted / idx_sorted receive the sorted keys (block << 28 | tile << 12 | cell) and
+// the user index of each sorted position.  Synchronises s.
+int plan_sort(const float* uv, int64_t M, const int64_t* off, int d, int K, int T, int tpa, uint2** packed,
+              std::vector<uint64_t>& keys_sorted, std::vector<int>& idx_sorted, hipStream_t s);
+// coord[k] = packed[order[k]] (device arrays of M).
+int plan_gather_coord(const uint2* packed, const int64_t* order, int64_t M, uint2* coord, hipStream_t s);
+
 // ---- DDE-aware G (dde.hip); used by the functions above when p.dde.on() ----
 int dde_degrid(const Plan& p, const int4* units, int nunits, const Item* items, const uint8_t* mask,
                const float2* grid, float2* out, const float2* y, const float2* v, double* part, hipStream_t s);

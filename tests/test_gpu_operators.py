@@ -320,3 +320,28 @@ def test_same_cell_pairs_match_oracle(R, bin):
     mask = np.array([1, 0, 1, 1], np.uint8)
     xm = plan.phi_adj(wt, mask=torch.tensor(mask, device="cuda")).cpu().numpy()
     assert rel_l2(xm, meas.phi_adj_real(w, blocks=np.flatnonzero(mask))) < TOL
+
+
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_plan_order_groups_blocks_and_tiles(R, tile):
+    """The plan's order (sorted on the device by block, tile and cell, then reordered inside
+    each work item) keeps every block's visibilities in that block's range and takes each
+    block's tiles in increasing order; tiles are recomputed here in FP64 from u-v, skipping
+    the visibilities within 1e-5 of a cell edge (where the rounding of either side may pick
+    the neighbour cell)."""
+    n, M, d = 128, 20000, 5
+    x, uv, off = problem(n, M, d, "lognormal", 9)
+    plan = R.Plan(n, uv, off, tile=tile, bin=256)
+    order = plan.order()
+    K = 2 * n
+    T = plan.tile
+    kap = np.mod(uv.astype(np.float64) * K / (2 * np.pi), K)
+    frac = kap - np.floor(kap)
+    cell = np.floor(kap).astype(np.int64) % K
+    tiles = (cell[:, 1] // T) * (K // T) + cell[:, 0] // T
+    clear = np.all(np.minimum(frac, 1.0 - frac) > 1e-5, axis=1)
+    for i in range(d):
+        idx = order[off[i]:off[i + 1]]
+        assert np.array_equal(np.sort(idx), np.arange(off[i], off[i + 1]))
+        t = tiles[idx][clear[idx]]
+        assert np.all(np.diff(t) >= 0)
