@@ -18,7 +18,8 @@
  *   (l_y, l_x) = (r - n/2, c - n/2).  n is a power of two, 16 <= n <= 2048.
  * Visibilities: complex float32, interleaved (re, im), M of them, stacked by data block
  *   as y = [y_1; ...; y_d] (Eq. 8).  Inside each block the library sorts visibilities
- *   into its own *plan order* (by grid tile and cell); every device visibility array
+ *   into its own *plan order* (by grid tile and cell, and within a work item of one tile
+ *   same-cell pairs and LDS banks); every device visibility array
  *   passed to or returned by the library is in plan order.  ri_plan_order() returns the
  *   map so the caller can permute its data once (see ri_plan_permute).
  * Masks: uint8 per block, nonzero = active (the set A of Algorithm 1, step 3).  A NULL
@@ -84,7 +85,10 @@ typedef struct {
  * Build a plan.  uv_host: M (u, v) float32 pairs in rad/px (host, user order);
  * block_off_host: d+1 offsets, block i = rows [block_off[i], block_off[i+1]) (host);
  * every block must be nonempty.  J must be 8; beta <= 0 selects 2.34 J.  tune may be NULL.
- * Allocates device memory; synchronises `stream` before returning.
+ * The coordinates are packed (cell and 20-bit fraction of the 2n x 2n grid, FP64) and sorted
+ * on the device (a stable radix sort by block, tile and cell); the work items are cut on the
+ * host.  Allocates device memory (and, while it runs, about 40 bytes per visibility of
+ * scratch); synchronises `stream` before returning.
  * Errors: RI_EINVAL (n not a power of two in [16, 2048], M < 1, d outside [1, 4096], empty block,
  * offsets not increasing, non-finite u-v), RI_ENOMEM, RI_EHIP.
  */
