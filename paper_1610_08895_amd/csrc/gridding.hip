@@ -90,7 +90,8 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
                                                const uint2* __restrict__ coord, const float2* __restrict__ grid, int K,
                                                int tpa, KBPoly P, float2* __restrict__ out,
                                                const float2* __restrict__ y, const float2* __restrict__ v,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, int ustride,
+                                               float2* __restrict__ zero_grid, const int* __restrict__ zero_tiles) {
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int NV = MAX_BIN / GT;
   constexpr int NWV = GT / 64;
@@ -99,7 +100,16 @@ __global__ __launch_bounds__(GT) void k_degrid(const int4* __restrict__ units, i
   __builtin_amdgcn_s_setprio(3);
   __shared__ float2 tile[TW * TP];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+  if (int(blockIdx.x) >= ustride) {
+    // a further workgroup: zeroes the interior of one tile without visibilities in
+    // zero_grid (a grid that the step's gridding will rebuild, untouched until then)
+    const int t = zero_tiles[blockIdx.x - ustride];
+    const int ty = t / tpa, tx = t - (t / tpa) * tpa;
+    for (int c = threadIdx.x; c < T * T; c += GT)
+      zero_grid[size_t(ty * T + c / T) * K + tx * T + c % T] = make_float2(0.f, 0.f);
+    return;
+  }
+  for (int u = blockIdx.x; u < nunits; u += ustride) {
     const int4 un = units[u];
     bool any = mask == nullptr && un.y < un.z;  // an empty unit fills a gap of the XCD order
     for (int q = un.y; q < un.z && !any; ++q) any = mask[items[q].x] != 0;
@@ -714,8 +724,8 @@ __global__ __launch_bounds__(GT) void k_zero_tiles(float2* __restrict__ grid, in
 template <int T, int MODE>
 int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const Item* items, const uint8_t* mask,
                 float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
-                bool with_halo = true, bool fresh = false) {
-  if (fresh && p.n_empty > 0) {
+                bool with_halo = true, bool fresh = false, bool zeroed = false) {
+  if (fresh && !zeroed && p.n_empty > 0) {
     hipLaunchKernelGGL((k_zero_tiles<T>), dim3(p.n_empty), dim3(GT), 0, s, grid, p.K, p.tpa, p.empty_tiles);
     RI_LAUNCH_CHECK();
   }
@@ -735,9 +745,9 @@ int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const
 template <int MODE>
 int grid_units(const Plan& p, bool sliced, const int4* units, int nunits, const Item* items, const uint8_t* mask,
                float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
-               bool with_halo = true, bool fresh = false) {
+               bool with_halo = true, bool fresh = false, bool zeroed = false) {
 #define RI_GRID_T(TT) \
-  launch_grid<TT, MODE>(p, sliced, units, nunits, items, mask, grid, y, e, v, shrink, s, with_halo, fresh)
+  launch_grid<TT, MODE>(p, sliced, units, nunits, items, mask, grid, y, e, v, shrink, s, with_halo, fresh, zeroed)
   switch (p.tile) {
     case 16: return RI_GRID_T(16);
     case 32: return RI_GRID_T(32);
@@ -779,12 +789,16 @@ int block_stats(const Plan& p, const uint8_t* mask, double* stats, double* out, 
 namespace {
 
 // Degridding over the plan's units (in XCD order, see create_plan).
+// zero: a grid whose tiles without visibilities further workgroups of the same launch
+// zero (or null).
 template <int T, int MODE>
 int degrid_batched_t(const Plan& p, const float2* grid, float2* out, const float2* y, const float2* v,
-                     double* part, const uint8_t* mask, hipStream_t s) {
-  if (p.n_dunits > 0) {
-    hipLaunchKernelGGL((k_degrid<T, MODE>), dim3(wgs_for(p, p.n_dunits)), dim3(GT), 0, s, p.dunits, p.n_dunits,
-                       p.titems, p.item_pairs, mask, p.coord, grid, p.K, p.tpa, p.poly, out, y, v, part);
+                     double* part, const uint8_t* mask, float2* zero, hipStream_t s) {
+  const int g = wgs_for(p, p.n_dunits), extra = zero != nullptr ? p.n_empty : 0;
+  if (p.n_dunits > 0 || extra > 0) {
+    hipLaunchKernelGGL((k_degrid<T, MODE>), dim3(g + extra), dim3(GT), 0, s, p.dunits, p.n_dunits, p.titems,
+                       p.item_pairs, mask, p.coord, grid, p.K, p.tpa, p.poly, out, y, v, part, g, zero,
+                       p.empty_tiles);
     RI_LAUNCH_CHECK();
   }
   return RI_OK;
@@ -792,11 +806,11 @@ int degrid_batched_t(const Plan& p, const float2* grid, float2* out, const float
 
 template <int MODE>
 int degrid_batched(const Plan& p, const float2* grid, float2* out, const float2* y, const float2* v, double* part,
-                   const uint8_t* mask, hipStream_t s) {
+                   const uint8_t* mask, hipStream_t s, float2* zero = nullptr) {
   switch (p.tile) {
-    case 16: return degrid_batched_t<16, MODE>(p, grid, out, y, v, part, mask, s);
-    case 32: return degrid_batched_t<32, MODE>(p, grid, out, y, v, part, mask, s);
-    case 64: return degrid_batched_t<64, MODE>(p, grid, out, y, v, part, mask, s);
+    case 16: return degrid_batched_t<16, MODE>(p, grid, out, y, v, part, mask, zero, s);
+    case 32: return degrid_batched_t<32, MODE>(p, grid, out, y, v, part, mask, zero, s);
+    case 64: return degrid_batched_t<64, MODE>(p, grid, out, y, v, part, mask, zero, s);
     default: return fail(RI_EINVAL, "unsupported tile %d", p.tile);
   }
 }
@@ -809,9 +823,12 @@ int degrid_apply(const Plan& p, const float2* grid, float2* y, const uint8_t* ma
 }
 
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
-                    const uint8_t* mask, hipStream_t s) {
-  if (p.dde.on()) return dde_degrid(p, p.dunits, p.n_dunits, p.titems, mask, grid, e, y, v, p.item_part, s);
-  return degrid_batched<DG_RESIDUAL>(p, grid, e, y, v, p.item_part, mask, s);
+                    const uint8_t* mask, hipStream_t s, float2* zero_empty) {
+  if (p.dde.on()) {
+    if (zero_empty != nullptr) return fail(RI_EINVAL, "degrid_residual: no tile zeroing with DDEs");
+    return dde_degrid(p, p.dunits, p.n_dunits, p.titems, mask, grid, e, y, v, p.item_part, s);
+  }
+  return degrid_batched<DG_RESIDUAL>(p, grid, e, y, v, p.item_part, mask, s, zero_empty);
 }
 
 int degrid_norms(const Plan& p, const float2* grid, const float2* y, const float2* v, double* part, hipStream_t s) {
@@ -825,7 +842,7 @@ int degrid_residual_block(const Plan& p, int block, const float2* grid, const fl
   if (p.dde.on()) return dde_degrid(p, p.bunits + a, b - a, p.items, nullptr, grid, e, y, v, p.item_part, s);
   const dim3 grid_dim(wgs_for(p, b - a));
 #define ARGS p.bunits + a, b - a, p.items, p.item_pairs, (const uint8_t*)nullptr, p.coord, grid, p.K, p.tpa, \
-             p.poly, e, y, v, p.item_part
+             p.poly, e, y, v, p.item_part, int(grid_dim.x), (float2*)nullptr, (const int*)nullptr
   RI_TILE_DISPATCH(k_degrid, DG_RESIDUAL)
 #undef ARGS
   RI_LAUNCH_CHECK();
@@ -855,10 +872,11 @@ int grid_project(const Plan& p, const float2* e, float2* v, const float* shrink,
                                 false);
 }
 
-int grid_project_all(const Plan& p, const float2* r, float2* v, const float* shrink, float2* grid, hipStream_t s) {
+int grid_project_all(const Plan& p, const float2* r, float2* v, const float* shrink, float2* grid, hipStream_t s,
+                     bool zeroed) {
   if (p.dde.on()) return fail(RI_EINVAL, "grid_project_all: the DDE kernels update the running sum instead");
   return grid_units<GR_FRESH>(p, true, p.units, p.n_units, p.titems, nullptr, grid, nullptr, r, v, shrink, s, false,
-                              true);
+                              true, zeroed);
 }
 
 int grid_halo(const Plan& p, float2* grid, hipStream_t s) {

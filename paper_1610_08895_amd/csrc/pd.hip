@@ -268,13 +268,15 @@ int ri_pd_step(ri_pd P, const uint8_t* mask, double* stats, hipStream_t stream) 
   // the join (the sparsity branch ends first) puts a wait between two queues on its path.
   const bool fork = !(P->timing && !ri::capturing(stream));
   if (fork) RI_HIP(hipEventRecord(P->ev_fork, stream));
+  // every block active (no mask): the sum is rebuilt from the new duals, reading r only
+  // (the degridding launch also zeroes its tiles without visibilities); otherwise the active
+  // blocks' changes are added to it
+  const bool fresh = mask == nullptr && !p.dde.on();
   RI_STAGE(P, RI_STAGE_DEGRID, stream,
-           ri::degrid_residual(p, p.grid, P->y, P->v, P->e, mask, stream));
+           ri::degrid_residual(p, p.grid, P->y, P->v, P->e, mask, stream, fresh ? P->sum : nullptr));
   RI_STAGE(P, RI_STAGE_BLOCK_NORMS, stream, ri::block_stats(p, mask, P->stats, stats, stream, P->eps, P->shrink));
-  // every block active (no mask): the sum is rebuilt from the new duals, reading r only;
-  // otherwise the active blocks' changes are added to it
-  if (mask == nullptr && !p.dde.on())
-    RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project_all(p, P->e, P->v, P->shrink, P->sum, stream));
+  if (fresh)
+    RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project_all(p, P->e, P->v, P->shrink, P->sum, stream, true));
   else
     RI_STAGE(P, RI_STAGE_GRID, stream, ri::grid_project(p, P->e, P->v, P->shrink, mask, P->sum, stream));
   RI_STAGE(P, RI_STAGE_GRID_HALO, stream, ri::grid_halo(p, P->sum, stream));

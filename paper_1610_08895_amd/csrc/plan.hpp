@@ -172,8 +172,10 @@ int grid_apply(const Plan& p, const float2* y, const uint8_t* mask, float2* grid
 // PD residual pass: r = v + G b - y stored in r_out; stats[2i] = ||r_i||^2, stats[2i+1] =
 // ||G_i b_i - y_i||^2 for the blocks whose items are processed (per-item partial sums, then
 // a per-block reduction).  All items (those of inactive blocks skipped), or one block's.
+// zero_empty (not with DDEs): a grid whose tiles without visibilities the same launch sets
+// to zero (for grid_project_all(..., zeroed = true), which then skips that).
 int degrid_residual(const Plan& p, const float2* grid, const float2* y, const float2* v, float2* e,
-                    const uint8_t* mask, hipStream_t s);
+                    const uint8_t* mask, hipStream_t s, float2* zero_empty = nullptr);
 // The norms of degrid_residual over all items, without storing e, into the given partials
 // (2 * PART_WAVES * n_items doubles).
 int degrid_norms(const Plan& p, const float2* grid, const float2* y, const float2* v, double* part, hipStream_t s);
@@ -186,7 +188,8 @@ int degrid_residual_block(const Plan& p, int block, const float2* grid, const fl
 int grid_project(const Plan& p, const float2* e, float2* v, const float* shrink, const uint8_t* mask, float2* grid,
                  hipStream_t s);
 // Adds the tile halos left by grid_project (which stores them) into the grid.
-int grid_project_all(const Plan& p, const float2* r, float2* v, const float* shrink, float2* grid, hipStream_t s);
+int grid_project_all(const Plan& p, const float2* r, float2* v, const float* shrink, float2* grid, hipStream_t s,
+                     bool zeroed = false);
 int grid_halo(const Plan& p, float2* grid, hipStream_t s);
 // y = Phi x over the blocks with mask[i] != 0 (mask may be null: all); x = Re Phi^dagger y.
 // y is complex interleaved (M), x real (n*n); both use the plan's work grid.
