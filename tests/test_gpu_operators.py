@@ -345,3 +345,32 @@ def test_plan_order_groups_blocks_and_tiles(R, tile):
         assert np.array_equal(np.sort(idx), np.arange(off[i], off[i + 1]))
         t = tiles[idx][clear[idx]]
         assert np.all(np.diff(t) >= 0)
+
+
+def _sparse_nudft(x, uv):
+    """Eq. 1 summed over the nonzero pixels only (FP64): y_m = sum_p x_p exp(-i (u l_x + v l_y))."""
+    n = x.shape[0]
+    r, c = np.nonzero(x)
+    ph = np.outer(uv[:, 0].astype(np.float64), c - n // 2) + np.outer(uv[:, 1].astype(np.float64), r - n // 2)
+    return np.exp(-1j * ph) @ x[r, c].astype(np.float64)
+
+
+@pytest.mark.parametrize("n,tile,d,M", [(2048, 16, 4096, 3 * 4096), (16, 16, 1, 1)])
+def test_plan_at_the_sort_key_limits(R, n, tile, d, M):
+    """The largest grid with the smallest tiles (2048^2: 256 x 256 tiles of 16 cells) and the
+    most blocks (4096), the limits of the device sort's keys, and a plan of one visibility:
+    Phi of a sparse sky against the direct sum of Eq. 1 for every visibility, and the blocks
+    kept in their ranges by the plan order."""
+    rng = np.random.default_rng(n + d)
+    x = np.zeros((n, n))
+    pos = rng.integers(0, n, (40, 2))
+    x[pos[:, 0], pos[:, 1]] = rng.uniform(0.1, 1.0, 40)
+    uv = rng.uniform(-np.pi, np.pi, (M, 2)).astype(np.float32)
+    off = np.linspace(0, M, d + 1).astype(np.int64)
+    plan = R.Plan(n, uv, off, tile=tile)
+    assert plan.tile == tile
+    order = plan.order()
+    for i in range(0, d, max(1, d // 64)):
+        assert np.array_equal(np.sort(order[off[i]:off[i + 1]]), np.arange(off[i], off[i + 1]))
+    y = to_user(plan.phi(torch.tensor(x, dtype=torch.float32, device="cuda")).cpu().numpy(), order)
+    assert rel_l2(y, _sparse_nudft(x, uv)) < TOL
