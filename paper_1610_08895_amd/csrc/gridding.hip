@@ -339,7 +339,8 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
                                                    const float2* __restrict__ e, float2* __restrict__ v,
                                                    const float* __restrict__ shrink,
                                                    const int* __restrict__ unit_patch, float2* __restrict__ spatch,
-                                                   int fresh, int ring_add) {
+                                                   int fresh, int ring_add, int ustride,
+                                                   const int* __restrict__ zero_tiles) {
   constexpr int TW = Pitch<T>::TW, TP = Pitch<T>::TP;
   constexpr int R0 = KB_J / 2 - 1;  // reach before the tile
   constexpr int NV = MAX_BIN / GGT;
@@ -441,8 +442,17 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
     }
   };
 
+  if (int(blockIdx.x) >= ustride) {
+    // a further workgroup of a fresh launch: zeroes the interior of one tile without
+    // visibilities, which no unit writes (dispatched after the units, in their tail)
+    const int t = zero_tiles[blockIdx.x - ustride];
+    const int ty = t / tpa, tx = t - (t / tpa) * tpa;
+    for (int c = threadIdx.x; c < T * T; c += GGT)
+      grid[size_t(ty * T + c / T) * K + tx * T + c % T] = make_float2(0.f, 0.f);
+    return;
+  }
   for (int k = threadIdx.x; k < 2 * TW * TP; k += GGT) (&acci[0][0])[k] = 0ull;
-  for (int u = blockIdx.x; u < nunits; u += gridDim.x) {
+  for (int u = blockIdx.x; u < nunits; u += ustride) {
     const int4 un = units[u];
     const int ty = un.x / tpa, tx = un.x - (un.x / tpa) * tpa;
 #pragma unroll
@@ -706,33 +716,20 @@ void launch_halo(const Plan& p, float2* grid, bool sliced, hipStream_t s) {
 
 // units/items: the plan's tile slices over titems (sliced = true) or one block's units
 // over items (whole tiles).
-// Zeroes the interiors of the plan's tiles without visibilities (a fresh gridding writes
-// every other tile's interior itself).
-template <int T>
-__global__ __launch_bounds__(GT) void k_zero_tiles(float2* __restrict__ grid, int K, int tpa,
-                                                   const int* __restrict__ tiles) {
-  const int t = tiles[blockIdx.x];
-  const int ty = t / tpa, tx = t - (t / tpa) * tpa;
-  for (int c = threadIdx.x; c < T * T; c += GT)
-    grid[size_t(ty * T + c / T) * K + tx * T + c % T] = make_float2(0.f, 0.f);
-}
-
-// fresh: the launch overwrites the grid (tile interiors stored, tiles without
-// visibilities zeroed) instead of adding into it.  Over the plan's tile slices (sliced)
+// fresh: the launch overwrites the grid (tile interiors stored, tiles without visibilities
+// zeroed by further workgroups of the launch unless `zeroed` says that is done) instead of
+// adding into it.  Over the plan's tile slices (sliced)
 // each tile's ring is overwritten; over one block's units it is added to, and the caller
 // zeroes the rings before the first block and runs the halo pass after the last.
 template <int T, int MODE>
 int launch_grid(const Plan& p, bool sliced, const int4* units, int nunits, const Item* items, const uint8_t* mask,
                 float2* grid, const float2* y, const float2* e, float2* v, const float* shrink, hipStream_t s,
                 bool with_halo = true, bool fresh = false, bool zeroed = false) {
-  if (fresh && !zeroed && p.n_empty > 0) {
-    hipLaunchKernelGGL((k_zero_tiles<T>), dim3(p.n_empty), dim3(GT), 0, s, grid, p.K, p.tpa, p.empty_tiles);
-    RI_LAUNCH_CHECK();
-  }
-  if (nunits > 0) {
-    hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(wgs_for(p, nunits)), dim3(GGT), 0, s, units, nunits, items,
-                       p.item_box, p.item_pairs, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, shrink,
-                       sliced ? p.unit_patch : nullptr, p.spatch, fresh ? 1 : 0, sliced ? 0 : 1);
+  const int g = wgs_for(p, nunits), extra = fresh && !zeroed ? p.n_empty : 0;
+  if (nunits > 0 || extra > 0) {
+    hipLaunchKernelGGL((k_grid_tiles<T, MODE>), dim3(g + extra), dim3(GGT), 0, s, units, nunits, items, p.item_box,
+                       p.item_pairs, mask, p.coord, grid, p.halo, p.K, p.tpa, p.poly, y, e, v, shrink,
+                       sliced ? p.unit_patch : nullptr, p.spatch, fresh ? 1 : 0, sliced ? 0 : 1, g, p.empty_tiles);
     RI_LAUNCH_CHECK();
   }
   if (with_halo) {
