@@ -73,7 +73,8 @@ int ri_hip_runtime_version(int* out);
 typedef struct {
   int tile;           /* grid tile side in cells (16, 32 or 64; default 32)            */
   int bin;            /* max visibilities per work item (<= 1024; default 1024)        */
-  int fft_panel;      /* columns per workgroup in the column FFT passes (default auto) */
+  int fft_panel;      /* reserved, must be 0 (the column FFT passes' panel width is fixed
+                         per grid size: 8 columns at K = 2048, measured best)             */
   int persistent_wgs; /* workgroups of the gather/scatter kernels (default: one per unit) */
   int slice_vis;      /* most visibilities one gridding workgroup accumulates for one
                          tile (default and negative: never split); a denser tile is
@@ -90,7 +91,8 @@ typedef struct {
  * host.  Allocates device memory (and, while it runs, about 40 bytes per visibility of
  * scratch); synchronises `stream` before returning.
  * Errors: RI_EINVAL (n not a power of two in [16, 2048], M < 1, d outside [1, 4096], empty block,
- * offsets not increasing, non-finite u-v), RI_ENOMEM, RI_EHIP.
+ * offsets not increasing, non-finite u-v, tile not 16, 32 or 64, bin above 1024, fft_panel not
+ * 0), RI_ENOMEM, RI_EHIP.
  */
 int ri_plan_create(ri_plan* out, int n, int64_t M, const float* uv_host, int d,
                    const int64_t* block_off_host, int J, double beta, const ri_tuning* tune,

@@ -157,7 +157,8 @@ int create_plan(Plan& p, int n, int64_t M, const float* uv, int d, const int64_t
   while (p.tile > 16 && p.tile > p.K / 2) p.tile /= 2;
   p.bin = tune && tune->bin > 0 ? tune->bin : MAX_BIN;
   if (p.bin > MAX_BIN) return fail(RI_EINVAL, "bin=%d exceeds %d", p.bin, MAX_BIN);
-  p.fft_panel = tune ? tune->fft_panel : 0;
+  if (tune && tune->fft_panel != 0) return fail(RI_EINVAL, "fft_panel is reserved and must be 0");
+  p.fft_panel = 0;
   p.persistent_wgs = tune ? tune->persistent_wgs : 0;
   p.slice_vis = tune && tune->slice_vis != 0 ? tune->slice_vis : -1;
   p.tpa = p.K / p.tile;

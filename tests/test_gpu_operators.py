@@ -193,6 +193,12 @@ def test_bad_arguments_raise(R):
         R.Plan(64, uv, [0, 5, 5, 10])                   # empty block
     with pytest.raises(RIError):
         R.Sara(40, 4)                                   # not divisible by 16
+    with pytest.raises(RIError):
+        R.Plan(64, uv, [0, 10], tile=48)                # tile not 16, 32 or 64
+    with pytest.raises(RIError):
+        R.Plan(64, uv, [0, 10], bin=2048)               # bin above 1024
+    with pytest.raises(RIError):
+        R.Plan(64, uv, [0, 10], fft_panel=4)            # reserved
     plan = R.Plan(64, uv, [0, 10])
     with pytest.raises(ValueError):
         plan.phi(torch.zeros(32, 32, device="cuda"))    # wrong image shape (host check)
