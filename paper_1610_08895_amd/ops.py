@@ -54,6 +54,7 @@ class Plan:
         L.check(lib.ri_plan_info(h, None, None, None, ctypes.byref(K), ctypes.byref(tl), ctypes.byref(ni)))
         self.K, self.tile, self.n_items = K.value, tl.value, ni.value
         self.block_off = off.copy()
+        self.jd = 0  # DDE kernel side (set_dde); 0: plain G
 
     @property
     def handle(self):
