@@ -60,7 +60,7 @@ enum { DG_APPLY = 0, DG_RESIDUAL = 1, DG_NORMS = 2 };  // NORMS: the residual's 
 template <int T>
 struct Pitch {
   static constexpr int TW = T + 8;  // region: the tile plus the kernel's reach
-  static constexpr int TP = T + 9;
+  static constexpr int TP = T + TILE_PAD;
 };
 
 // Position of region cell (ly, lx), outside the tile interior [R0, R0 + T)^2, in the tile's
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   float2 acc[NC];
   // Only the slices of cells that meet the box's rows are visited (a test that is the same
   // for the whole workgroup); cells outside the box were never touched and read as zero.
-  static_assert(TP == TW + 1, "cell c of the region sits at c + c / TW in the pitched tile");
+  static_assert(TP > TW, "pitched rows");
   auto fold = [&](int buf, uint32_t box, float inv) {
     const int r0 = box & 255u, r1 = int((box >> 8) & 255u) + KB_J;
 #pragma unroll
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
       if ((j * GGT + GGT - 1) / TW < r0 || (j * GGT) / TW >= r1) continue;
       const int c = threadIdx.x + j * GGT;
       if (c < TW * TW) {
-        unsigned long long* cell = &acci[buf][c + c / TW];
+        unsigned long long* cell = &acci[buf][(c / TW) * TP + c % TW];
         const unsigned long long w64 = *cell;
         if (w64) {
           *cell = 0ull;

@@ -70,7 +70,7 @@ using KV = std::pair<uint64_t, int64_t>;  // (tile << 32 | tile-local cell ly * 
 
 // Reorders a list of visibilities (or of same-cell pairs, by their first member) so that
 // every 64 consecutive ones, which one wavefront processes together, spread their
-// staged-tile addresses ly * (T + 9) + lx evenly over the LDS banks: they are dealt
+// staged-tile addresses ly * (T + TILE_PAD) + lx evenly over the LDS banks: they are dealt
 // round-robin from one queue per bank (32 banks of 8-byte words).
 template <class E, class Key>
 void lds_bank_order(std::vector<E>& v, int T, Key key) {
@@ -79,7 +79,7 @@ void lds_bank_order(std::vector<E>& v, int T, Key key) {
   for (const E& e : v) {
     const uint32_t local = uint32_t(key(e));
     const uint32_t ly = local / T, lx = local % T;
-    q[(ly * uint32_t(T + 9) + lx) % NB].push_back(e);
+    q[(ly * uint32_t(T + TILE_PAD) + lx) % NB].push_back(e);
   }
   size_t head[NB] = {}, out = 0;
   while (out < v.size())

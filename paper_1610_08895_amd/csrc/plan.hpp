@@ -50,6 +50,10 @@ __device__ __forceinline__ void kb_weights(unsigned packed, const KBPoly& P, flo
 using Item = int4;
 constexpr int MAX_BIN = 1024;    // largest `bin` (4 visibilities per thread of a gridding workgroup)
 constexpr int GRID_LANES = 256;  // threads per workgroup of the tile gridding
+// LDS row pitch of a staged tile region in 8-byte cells: the region's width T + 8 plus
+// TILE_PAD - 8 more, so that consecutive rows start in different LDS banks (the plan deals
+// a wavefront's visibilities over the banks of this layout)
+constexpr int TILE_PAD = 9;
 constexpr int DUNIT_VIS = 2048;  // visibilities per degridding unit (several items of one tile)
 constexpr int PART_WAVES = 4;    // FP64 norm partials per work item (one per wavefront)
 // Cells of a tile's halo ring: its (tile + 8)^2 region (the tile and the kernel's reach)
