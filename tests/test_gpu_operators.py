@@ -298,17 +298,17 @@ def test_light_units_match_oracle(R, tile):
     assert rel_l2(xm, meas.phi_adj_real(w, blocks=np.flatnonzero(mask))) < TOL
 
 
-@pytest.mark.parametrize("bin", [1024, 600, 320, 64])
-def test_same_cell_pairs_match_oracle(R, bin):
-    """Visibilities crowded one to eight to a cell over a few tiles, so that the plan pairs
+@pytest.mark.parametrize("bin,crowd", [(1024, 8), (1024, 16), (600, 8), (320, 8), (64, 8)])
+def test_same_cell_pairs_match_oracle(R, bin, crowd):
+    """Visibilities crowded one to `crowd` to a cell over a few tiles, so that the plan pairs
     same-cell visibilities in whole wavefronts (items of up to `bin`: both slot pairs, one,
     or none when an item is too small), with odd counts left single and ragged blocks;
     Phi, Phi^dagger and masked Phi^dagger against the oracle."""
     n = 64
     K = 2 * n
-    rng = np.random.default_rng(77 + bin)
+    rng = np.random.default_rng(77 + bin + 1000 * crowd)
     cells = rng.integers(0, 40, (700, 2))
-    counts = rng.integers(1, 9, 700)
+    counts = rng.integers(1, crowd + 1, 700)
     kap = np.repeat(cells, counts, axis=0) + rng.uniform(0.0, 1.0, (int(counts.sum()), 2))
     uv = 2 * np.pi * kap / K
     uv = np.where(uv >= np.pi, uv - 2 * np.pi, uv).astype(np.float32)
