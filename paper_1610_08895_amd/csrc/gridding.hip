@@ -345,7 +345,10 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   constexpr int R0 = KB_J / 2 - 1;  // reach before the tile
   constexpr int NV = MAX_BIN / GGT;
   constexpr int NWV = GGT / 64;
-  constexpr int NC = (TW * TW + GGT - 1) / GGT;  // region cells per thread
+  // region cells per thread: thread t owns the words t + j GGT of the pitched layout (the
+  // pad column included), so that its cells lie a whole number of 512-byte strides apart
+  // and two of them move with one LDS instruction
+  constexpr int NC = (TW * TP + GGT - 1) / GGT;
   static_assert(NV == 4, "two slot pairs per thread (item_order)");
   // the data branch's kernels issue ahead of the sparsity branch's waves sharing their SIMDs
   __builtin_amdgcn_s_setprio(3);
@@ -423,20 +426,24 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   static_assert(TP > TW, "pitched rows");
   auto fold = [&](int buf, uint32_t box, float inv) {
     const int r0 = box & 255u, r1 = int((box >> 8) & 255u) + KB_J;
+    // slices are taken two at a time (one row test, and two cells per LDS instruction)
 #pragma unroll
-    for (int j = 0; j < NC; ++j) {
-      if ((j * GGT + GGT - 1) / TW < r0 || (j * GGT) / TW >= r1) continue;
-      const int c = threadIdx.x + j * GGT;
-      if (c < TW * TW) {
-        unsigned long long* cell = &acci[buf][(c / TW) * TP + c % TW];
-        const unsigned long long w64 = *cell;
-        if (w64) {
+    for (int j = 0; j < NC; j += 2) {
+      const int jn = j + 1 < NC ? 2 : 1;
+      if ((j * GGT + jn * GGT - 1) / TP < r0 || (j * GGT) / TP >= r1) continue;
+#pragma unroll
+      for (int h = 0; h < jn; ++h) {
+        const int c = threadIdx.x + (j + h) * GGT;
+        if ((j + h + 1) * GGT <= TW * TP || c < TW * TP) {
+          unsigned long long* cell = &acci[buf][c];
+          const unsigned long long w64 = *cell;
           *cell = 0ull;
+          // Re is the low field as a signed integer; Im is the high field plus the borrow
+          // that a negative Re took from it
           const int ir = static_cast<int>(static_cast<unsigned>(w64));
-          const int ii = static_cast<int>(static_cast<unsigned>((w64 - static_cast<unsigned long long>(
-                                                                          static_cast<long long>(ir))) >> 32));
-          acc[j].x += float(ir) * inv;
-          acc[j].y += float(ii) * inv;
+          const int ii = static_cast<int>(static_cast<unsigned>(w64 >> 32) + (static_cast<unsigned>(ir) >> 31));
+          acc[j + h].x = fmaf(float(ir), inv, acc[j + h].x);
+          acc[j + h].y = fmaf(float(ii), inv, acc[j + h].y);
         }
       }
     }
@@ -573,8 +580,9 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
       // hides that they do not change): keeping them across the unit loop costs registers
       int c = threadIdx.x + j * GGT;
       asm volatile("" : "+v"(c));
-      if (c >= TW * TW) continue;
-      const int ly = c / TW, lx = c - (c / TW) * TW;
+      if (c >= TW * TP) continue;
+      const int ly = c / TP, lx = c - (c / TP) * TP;
+      if (lx >= TW) continue;  // the pad column
       const float2 a = acc[j];
       const bool inside = ly >= R0 && ly < R0 + T && lx >= R0 && lx < R0 + T;
       if (inside && sp < 0) {
@@ -594,7 +602,7 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
           *h = make_float2(old.x + a.x, old.y + a.y);
         }
       } else {
-        patch[c] = a;  // a further slice's whole region
+        patch[ly * TW + lx] = a;  // a further slice's whole region
       }
     }
   }
