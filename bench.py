@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--plain-steps", type=int, default=20)
-    ap.add_argument("--op-reps", type=int, default=20)
+    ap.add_argument("--op-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="eager steps only (for counter runs)")
     ap.add_argument("--workload", default=WORKLOAD, choices=["n1024_m4m_d64", "n2048_m16m_d128"],
