@@ -157,13 +157,15 @@ def time_run(sol, schedule, warmup, steps, refresh=64, seed=0, reweight=None):
 
 
 def time_ops(plan, x, y, reps):
-    """Mean ms of Phi and of Phi^dagger (HIP events on the current stream)."""
+    """Mean ms of Phi and of Phi^dagger (HIP events on the current stream), after as many
+    untimed calls of each (the GPU's clocks take tens of milliseconds to settle after the
+    host-bound parts of the run)."""
     import torch
 
     yb = torch.empty(plan.M, dtype=torch.complex64, device="cuda")
     xb = torch.empty(plan.n, plan.n, dtype=torch.float32, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    for _ in range(3):
+    for _ in range(max(3, reps)):
         plan.phi(x, yb)
         plan.phi_adj(y, xb)
     ev[0].record()
