@@ -356,8 +356,23 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
   __shared__ float red_b[2][NWV], red_m[2][NWV];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 
+  // with a mask, the current unit's active items as bits (item act_base + k: bit k), every
+  // lane testing one item at once; a unit of more than 64 items tests them one by one
+  const bool masked = MODE != GR_FRESH && mask != nullptr;
+  unsigned long long act = 0ull;
+  int act_base = 0;
+  bool bits = false;
+  auto is_active = [&](int q) {
+    return bits ? ((act >> (q - act_base)) & 1ull) != 0ull : mask[items[q].x] != 0;
+  };
   auto next_active = [&](int q, int end) {
-    while (q < end && MODE != GR_FRESH && mask != nullptr && mask[items[q].x] == 0) ++q;
+    if (!masked) return q;
+    if (bits) {
+      const int o = q - act_base;
+      const unsigned long long m = o < 64 ? act >> o : 0ull;
+      return m != 0ull ? q + __builtin_ctzll(m) : end;
+    }
+    while (q < end && mask[items[q].x] == 0) ++q;
     return q;
   };
   // operands of the current item, and the raw loads of the next one
@@ -469,7 +484,12 @@ __global__ __launch_bounds__(GGT, grid_waves_per_simd<T>()) void k_grid_tiles(co
     int q = un.y, buf = 0;
     Item it = items[q];
     load_raw(it);
-    if (MODE != GR_FRESH && mask != nullptr && mask[it.x] == 0) {
+    if (masked) {
+      bits = un.z - un.y <= 64;
+      act_base = un.y;
+      if (bits) act = __ballot(lane < un.z - un.y && mask[items[un.y + lane].x] != 0);
+    }
+    if (masked && !is_active(q)) {
       q = next_active(q + 1, un.z);
       if (q < un.z) {
         it = items[q];
