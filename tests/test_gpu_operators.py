@@ -125,6 +125,30 @@ def test_phi_masks_touch_only_active_blocks(R):
     assert torch.count_nonzero(xz).item() == 0
 
 
+@pytest.mark.parametrize("d", [40, 200])
+def test_masked_adjoint_with_many_blocks_per_tile(R, d):
+    """Every block spread over the whole u-v plane (40 visibilities each over 4 x 4 tiles), so
+    that a tile holds an item of nearly every block: with d = 40 a unit's active items are
+    found with one wavefront ballot (at most 64 items), with d = 200 they are tested one by
+    one.  Masked Phi^dagger for two masks against the oracle; an empty mask gives zero."""
+    n = 32
+    rng = np.random.default_rng(500 + d)
+    M = 40 * d
+    uv = rng.uniform(-np.pi, np.pi, (M, 2)).astype(np.float32)
+    off = np.arange(0, M + 1, 40, dtype=np.int64)
+    plan = R.Plan(n, uv, off, tile=16, bin=64)
+    assert plan.tile == 16
+    order = plan.order()
+    meas = Measurement(uv, off, (n, n))
+    w = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    wt = torch.tensor(to_plan(w, order), dtype=torch.complex64, device="cuda")
+    for mask in ((rng.random(d) < 0.5).astype(np.uint8), (np.arange(d) % 7 == 3).astype(np.uint8)):
+        xa = plan.phi_adj(wt, mask=torch.tensor(mask, device="cuda")).cpu().numpy()
+        assert rel_l2(xa, meas.phi_adj_real(w, blocks=np.flatnonzero(mask))) < TOL
+    xz = plan.phi_adj(wt, mask=torch.zeros(d, dtype=torch.uint8, device="cuda"))
+    assert torch.count_nonzero(xz).item() == 0
+
+
 def test_gpu_adjoint_dot_product(R):
     n, M, d = 128, 40000, 8
     x, uv, off = problem(n, M, d, "lognormal", 4)
