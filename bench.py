@@ -58,7 +58,7 @@ def stage_bytes(n, M_active, wavelets=8):
     per visibility), following the minimal fused design of the method's per-iteration data
     flow: the degridding reads coordinates, y and v and writes r (32 B per visibility) and
     reads the grid once (32N); the gridding of step 9 reads r and the coordinates and writes
-    v (24 B per visibility) and writes its grid once (32N).  This build's own extra traffic
+    v (24 B per visibility) and writes its grid once (32N).  The library's own extra traffic
     (its running grid sum, the separate halo pass) is not counted as algorithmic."""
     N = n * n
     nw = wavelets
@@ -203,8 +203,8 @@ def main():
                     help="also copy a buffer of this many MiB once (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not part of "
-              "this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library runs one process "
+              "per GPU and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
