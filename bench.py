@@ -190,6 +190,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="eager steps only (for counter runs)")
     ap.add_argument("--workload", default=WORKLOAD, choices=["n1024_m4m_d64", "n2048_m16m_d128"],
                     help="workload of the headline section (profiling runs of the large case)")
+    ap.add_argument("--adaptive-only", action="store_true",
+                    help="profiling aid: time only the Eq. 14 step at 16 of 64 blocks (graph-replayed) and "
+                         "print its line, no JSON")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the adaptive and 2048^2 operating points (for short profiling runs)")
     ap.add_argument("--tile", type=int, default=0, help="grid tile side (0: the autotuner's pick)")
@@ -251,6 +254,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+
+    if args.adaptive_only:
+        sol_a = Solver(plan, sara, y_plan, eps, psi_norm, phi_norm)
+        sch = Schedule("adaptive", n_nodes=16.0, p_min=0.05, p_max=0.5)
+        ms_a, nb_a, nv_a = time_run(sol_a, sch, args.warmup, args.steps, seed=1)
+        log(f"adaptive16: {ms_a:.4f} ms/iter, {nb_a:.1f} blocks / {nv_a / 1e6:.2f} M vis active")
+        return
 
     # ---- headline: p = 1, graph-replayed iterations, running-sum refresh every 64 ----
     sol = Solver(plan, sara, y_plan, eps, psi_norm, phi_norm)
